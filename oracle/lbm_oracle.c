@@ -1,0 +1,471 @@
+/*
+ * lbm_oracle.c -- FP64 CPU reference for the rectangular-lattice central
+ * moment LBM (RC-LBM) and its raw-moment special case (RNR-LBM) of
+ * E. Yahia & K. N. Premnath, "Central Moment Lattice Boltzmann Method on a
+ * Rectangular Lattice" (arXiv 2103.02119).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the CPU
+ * baseline of the benchmark.  The product path never calls it.
+ *
+ * Deliberately written in the paper's matrix-vector form (the paper itself
+ * recommends component form for speed, Sec. 3; this file does the opposite
+ * so that it shares no structure with the GPU path).  Each step follows the
+ * order of Sec. 3 / Sec. 4: moments, relaxation, back-transform, stream,
+ * update of the hydrodynamic fields.
+ *
+ * Readings taken where the printed text is garbled or silent (each one is
+ * listed with its justification in the design notes of the repository):
+ *   - velocity ordering from Eq. 2 (Eq. 1 is garbled);
+ *   - T is built from the basis definition Eq. 3; Eq. 4 row 7 prints "a"
+ *     where e_x e_y^2 of (1, a) is a^2;
+ *   - T^{-1} (App. A) row 0 column 8 is +1/a^2 (printed -1/a^2);
+ *   - Eq. 12, m_8: coefficient of rho cs^2 (ux^2 + uy^2) is 1, as the
+ *     binomial transform of the central equilibria (Eq. 49) requires;
+ *   - dt = 1 multiplies the corrections; d rho by central differences at the
+ *     same time level as f, with y spacing a; at a wall the missing
+ *     neighbour's density is the node's own density;
+ *   - the non-equilibrium moments in Eq. 37-38 are the raw ones of
+ *     Eq. 34-35 (m - m^{eq,r}), with no forcing term;
+ *   - bounce-back: f_i(x_f, t+1) = ft_ibar(x_f, t) - (feq_ibar - feq_i)(rho_w, u_w)
+ *     with rho_w = rho0; a link that crosses a moving wall uses that wall.
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Eq. 2: e_x = CX, e_y = a * CY for i = 0..8. */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+/* e_ibar = -e_i */
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+static void matvec9(const double *M, const double *v, double *out)
+{
+    for (int r = 0; r < 9; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < 9; ++c)
+            s += M[r * 9 + c] * v[c];
+        out[r] = s;
+    }
+}
+
+/* Eq. 3: T = [|1>, |ex>, |ey>, |ex^2+ey^2>, |ex^2-ey^2>, |ex ey>, |ex^2 ey>,
+ * |ex ey^2>, |ex^2 ey^2>] as rows, evaluated on the velocity set of Eq. 2. */
+void orc_T(double a, double *T)
+{
+    for (int k = 0; k < 9; ++k) {
+        const double ex = CX[k], ey = a * CY[k];
+        T[0 * 9 + k] = 1.0;
+        T[1 * 9 + k] = ex;
+        T[2 * 9 + k] = ey;
+        T[3 * 9 + k] = ex * ex + ey * ey;
+        T[4 * 9 + k] = ex * ex - ey * ey;
+        T[5 * 9 + k] = ex * ey;
+        T[6 * 9 + k] = ex * ex * ey;
+        T[7 * 9 + k] = ex * ey * ey;
+        T[8 * 9 + k] = ex * ex * ey * ey;
+    }
+}
+
+/* App. A, Eq. (Tinverse), with r1, r2 as defined there and the sign of
+ * row 0 / column 8 read as +1/a^2. */
+void orc_Tinv(double a, double *Ti)
+{
+    const double a2 = a * a;
+    const double r1 = -0.5 * (1.0 + 1.0 / a2);
+    const double r2 = -0.5 * (1.0 - 1.0 / a2);
+    const double h = 0.5, q = 0.25;
+    const double M[9][9] = {
+        {1, 0, 0, r1, r2, 0, 0, 0, 1.0 / a2},
+        {0, h, 0, q, q, 0, 0, -h / a2, -h / a2},
+        {0, 0, h / a, q / a2, -q / a2, 0, -h / a, 0, -h / a2},
+        {0, -h, 0, q, q, 0, 0, h / a2, -h / a2},
+        {0, 0, -h / a, q / a2, -q / a2, 0, h / a, 0, -h / a2},
+        {0, 0, 0, 0, 0, q / a, q / a, q / a2, q / a2},
+        {0, 0, 0, 0, 0, -q / a, q / a, -q / a2, q / a2},
+        {0, 0, 0, 0, 0, q / a, -q / a, -q / a2, q / a2},
+        {0, 0, 0, 0, 0, -q / a, -q / a, q / a2, q / a2},
+    };
+    memcpy(Ti, M, sizeof(M));
+}
+
+/* App. B, Eq. 53: frame transformation F(u) from raw to central moments.
+ * Its inverse is F(-u) (Eq. 55). */
+void orc_F(double ux, double uy, double *F)
+{
+    const double ux2 = ux * ux, uy2 = uy * uy;
+    const double M[9][9] = {
+        {1, 0, 0, 0, 0, 0, 0, 0, 0},
+        {-ux, 1, 0, 0, 0, 0, 0, 0, 0},
+        {-uy, 0, 1, 0, 0, 0, 0, 0, 0},
+        {ux2 + uy2, -2 * ux, -2 * uy, 1, 0, 0, 0, 0, 0},
+        {ux2 - uy2, -2 * ux, 2 * uy, 0, 1, 0, 0, 0, 0},
+        {ux * uy, -uy, -ux, 0, 0, 1, 0, 0, 0},
+        {-ux2 * uy, 2 * ux * uy, ux2, -0.5 * uy, -0.5 * uy, -2 * ux, 1, 0, 0},
+        {-ux * uy2, uy2, 2 * ux * uy, -0.5 * ux, 0.5 * ux, -2 * uy, 0, 1, 0},
+        {ux2 * uy2, -2 * ux * uy2, -2 * ux2 * uy, 0.5 * (ux2 + uy2), 0.5 * (uy2 - ux2),
+         4 * ux * uy, -2 * uy, -2 * ux, 1},
+    };
+    memcpy(F, M, sizeof(M));
+}
+
+/* Sec. 3 / Sec. 4, "update hydrodynamic fields":
+ * rho = sum f, rho u = sum f e + F/2 (dt = 1). */
+void orc_macro(const orc_params *p, const double *f9, double *rho, double *ux, double *uy)
+{
+    double r = 0.0, jx = 0.0, jy = 0.0;
+    for (int k = 0; k < 9; ++k) {
+        r += f9[k];
+        jx += f9[k] * CX[k];
+        jy += f9[k] * (p->a * CY[k]);
+    }
+    *rho = r;
+    *ux = (jx + 0.5 * p->force[0]) / r;
+    *uy = (jy + 0.5 * p->force[1]) / r;
+}
+
+/* Equilibrium populations: raw equilibria are the binomial transform of the
+ * central equilibria (Sec. 2.1, text before Eq. 12), so
+ * feq = T^{-1} F(-u) (rho, 0, 0, 2 rho cs^2, 0, 0, 0, 0, rho cs^4)
+ * -- Eq. 49 without the corrections. */
+void orc_feq(const orc_params *p, double rho, double ux, double uy, double *feq9)
+{
+    const double s = p->cs2;
+    const double mceq[9] = {rho, 0, 0, 2 * rho * s, 0, 0, 0, 0, rho * s * s};
+    double Finv[81], Ti[81], m[9];
+    orc_F(-ux, -uy, Finv);
+    orc_Tinv(p->a, Ti);
+    matvec9(Finv, mceq, m);
+    matvec9(Ti, m, feq9);
+}
+
+/* Eq. 12 (square-lattice raw equilibria), m_8 coefficient read as 1. */
+static void raw_equilibria(double rho, double ux, double uy, double s, double *meq)
+{
+    meq[0] = rho;
+    meq[1] = rho * ux;
+    meq[2] = rho * uy;
+    meq[3] = 2 * rho * s + rho * (ux * ux + uy * uy);
+    meq[4] = rho * (ux * ux - uy * uy);
+    meq[5] = rho * ux * uy;
+    meq[6] = s * rho * uy + rho * ux * ux * uy;
+    meq[7] = s * rho * ux + rho * ux * uy * uy;
+    meq[8] = rho * s * s + rho * s * (ux * ux + uy * uy) + rho * ux * ux * uy * uy;
+}
+
+/* Eq. 13 (raw source moments). */
+static void raw_sources(double Fx, double Fy, double ux, double uy, double *phi)
+{
+    phi[0] = 0.0;
+    phi[1] = Fx;
+    phi[2] = Fy;
+    phi[3] = 2 * (Fx * ux + Fy * uy);
+    phi[4] = 2 * (Fx * ux - Fy * uy);
+    phi[5] = Fx * uy + Fy * ux;
+    phi[6] = Fy * ux * ux + 2 * Fx * ux * uy;
+    phi[7] = Fx * uy * uy + 2 * Fy * uy * ux;
+    phi[8] = 2 * (Fx * ux * uy * uy + Fy * uy * ux * ux);
+}
+
+/* Eq. 37-38 with the coefficients of Eq. 40; the bracketed non-equilibrium
+ * moments are eta - m^{eq,r} of Eq. 34-35. */
+static void strain_rate_from(const orc_params *p, const double *m, double rho, double ux,
+                             double uy, double gx, double gy, double *X, double *Y)
+{
+    const double s = p->cs2, a2 = p->a * p->a;
+    const double w3 = p->omega[3], w4 = p->omega[4];
+    const double m3eqr = 2 * rho * s + rho * (ux * ux + uy * uy);
+    const double m4eqr = rho * (ux * ux - uy * uy);
+
+    const double B1 = rho * (-2 * s / w3 - (-3 * s + 1) / 2 + 3 * ux * ux / 2);
+    const double B2 = rho * (-2 * s / w3 - (-3 * s + a2) / 2 + 3 * uy * uy / 2);
+    const double B3 = ((3 * s - 1) / 2) * ux;
+    const double B4 = ((3 * s - a2) / 2) * uy;
+    const double C1 = rho * (-2 * s / w4 - (-3 * s + 1) / 2 + 3 * ux * ux / 2);
+    const double C2 = rho * (2 * s / w4 - (3 * s - a2) / 2 - 3 * uy * uy / 2);
+    const double C3 = ((3 * s - 1) / 2) * ux;
+    const double C4 = ((-3 * s + a2) / 2) * uy;
+
+    const double M3 = m[3] - m3eqr - B3 * gx - B4 * gy;
+    const double M4 = m[4] - m4eqr - C3 * gx - C4 * gy;
+    *X = (C2 * M3 - B2 * M4) / (C2 * B1 - C1 * B2);
+    *Y = (C1 * M3 - B1 * M4) / (C1 * B2 - C2 * B1);
+}
+
+/* Eq. 23-26 (with Eq. 27: no correction on m_5), dt = 1. */
+static void corrections_from(const orc_params *p, double rho, double ux, double uy, double gx,
+                             double gy, double X, double Y, double *d3, double *d4)
+{
+    if (!p->corrections) {
+        *d3 = 0.0;
+        *d4 = 0.0;
+        return;
+    }
+    const double s = p->cs2, a2 = p->a * p->a;
+    const double k3 = 1.0 / p->omega[3] - 0.5;
+    const double k4 = 1.0 / p->omega[4] - 0.5;
+    const double m3s = k3 * ((-3 * s + 1) * rho * X + (-3 * s + a2) * rho * Y +
+                             (-3 * s + 1) * ux * gx + (-3 * s + a2) * uy * gy);
+    const double m4s = k4 * ((-3 * s + 1) * rho * X + (3 * s - a2) * rho * Y +
+                             (-3 * s + 1) * ux * gx + (3 * s - a2) * uy * gy);
+    const double m3G = -3 * rho * k3 * (ux * ux * X + uy * uy * Y);
+    const double m4G = -3 * rho * k4 * (ux * ux * X - uy * uy * Y);
+    *d3 = m3s + m3G;
+    *d4 = m4s + m4G;
+}
+
+void orc_strain_rate(const orc_params *p, const double *f9, double drho_dx, double drho_dy,
+                     double *dux_dx, double *duy_dy)
+{
+    double T[81], m[9], rho, ux, uy;
+    orc_T(p->a, T);
+    matvec9(T, f9, m);
+    orc_macro(p, f9, &rho, &ux, &uy);
+    strain_rate_from(p, m, rho, ux, uy, drho_dx, drho_dy, dux_dx, duy_dy);
+}
+
+void orc_corrections(const orc_params *p, const double *f9, double drho_dx, double drho_dy,
+                     double *delta3, double *delta4)
+{
+    double T[81], m[9], rho, ux, uy, X, Y;
+    orc_T(p->a, T);
+    matvec9(T, f9, m);
+    orc_macro(p, f9, &rho, &ux, &uy);
+    strain_rate_from(p, m, rho, ux, uy, drho_dx, drho_dy, &X, &Y);
+    corrections_from(p, rho, ux, uy, drho_dx, drho_dy, X, Y, delta3, delta4);
+}
+
+/* One node's collision.  T and Ti are passed in so the field loops build
+ * them once. */
+static void collide_with(const orc_params *p, const double *T, const double *Ti,
+                         const double *f9, double gx, double gy, double *out9)
+{
+    const double s = p->cs2;
+    const double *w = p->omega;
+    const double Fx = p->force[0], Fy = p->force[1];
+    double rho, ux, uy, X, Y, d3, d4;
+    double m[9], mt[9];
+
+    /* pre-collision raw moments m = T f */
+    matvec9(T, f9, m);
+    orc_macro(p, f9, &rho, &ux, &uy);
+    /* local strain rate (Eq. 37-38) and corrections (Eq. 23-27) */
+    strain_rate_from(p, m, rho, ux, uy, gx, gy, &X, &Y);
+    corrections_from(p, rho, ux, uy, gx, gy, X, Y, &d3, &d4);
+
+    if (p->collision == ORC_RC) {
+        /* Sec. 4: m^c = F m; relax toward Eq. 49 with central sources
+         * (0, Fx, Fy, 0, ...); back with F^{-1} = F(-u). */
+        double F[81], Finv[81], mc[9], mct[9];
+        const double mceq[9] = {rho, 0, 0, 2 * rho * s + d3, d4, 0.0, 0, 0, rho * s * s};
+        const double phic[9] = {0, Fx, Fy, 0, 0, 0, 0, 0, 0};
+        orc_F(ux, uy, F);
+        orc_F(-ux, -uy, Finv);
+        matvec9(F, m, mc);
+        for (int j = 0; j < 9; ++j)
+            mct[j] = mc[j] + w[j] * (mceq[j] - mc[j]) + (1 - w[j] / 2) * phic[j];
+        matvec9(Finv, mct, mt);
+    } else {
+        /* Sec. 3: relax raw moments toward m^{eq,r} + corrections (Eq. 10)
+         * with the sources of Eq. 13. */
+        double meq[9], phi[9];
+        raw_equilibria(rho, ux, uy, s, meq);
+        meq[3] += d3;
+        meq[4] += d4;
+        raw_sources(Fx, Fy, ux, uy, phi);
+        for (int j = 0; j < 9; ++j)
+            mt[j] = m[j] + w[j] * (meq[j] - m[j]) + (1 - w[j] / 2) * phi[j];
+    }
+    /* post-collision populations f~ = T^{-1} m~ */
+    matvec9(Ti, mt, out9);
+}
+
+void orc_collide_node(const orc_params *p, const double *f9, double drho_dx, double drho_dy,
+                      double *out9)
+{
+    double T[81], Ti[81];
+    orc_T(p->a, T);
+    orc_Tinv(p->a, Ti);
+    collide_with(p, T, Ti, f9, drho_dx, drho_dy, out9);
+}
+
+/* ---------------------------------------------------------------- fields */
+
+#define IDX(p, j, i) ((size_t)(j) * (size_t)(p)->nx + (size_t)(i))
+#define FIDX(p, k, j, i) ((size_t)(k) * (size_t)(p)->nx * (size_t)(p)->ny + IDX(p, j, i))
+
+static void gather9(const orc_params *p, const double *f, int i, int j, double *f9)
+{
+    for (int k = 0; k < 9; ++k)
+        f9[k] = f[FIDX(p, k, j, i)];
+}
+
+void orc_init(const orc_params *p, const double *rho, const double *ux, const double *uy,
+              double *f)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            double feq[9];
+            const size_t n = IDX(p, j, i);
+            orc_feq(p, rho ? rho[n] : p->rho0, ux ? ux[n] : 0.0, uy ? uy[n] : 0.0, feq);
+            for (int k = 0; k < 9; ++k)
+                f[FIDX(p, k, j, i)] = feq[k];
+        }
+}
+
+void orc_density(const orc_params *p, const double *f, double *rho)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            double r = 0.0;
+            for (int k = 0; k < 9; ++k)
+                r += f[FIDX(p, k, j, i)];
+            rho[IDX(p, j, i)] = r;
+        }
+}
+
+/* Central differences (the paper computes the density gradient "using a
+ * central difference approach"); x spacing 1, y spacing a.  Across a
+ * periodic face the neighbour wraps; across a wall it is the node itself. */
+void orc_density_gradient(const orc_params *p, const double *rho, double *gx, double *gy)
+{
+    const int nx = p->nx, ny = p->ny;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+            if (im < 0) im = (p->bc_type[0] == ORC_PERIODIC) ? nx - 1 : i;
+            if (ip >= nx) ip = (p->bc_type[1] == ORC_PERIODIC) ? 0 : i;
+            if (jm < 0) jm = (p->bc_type[2] == ORC_PERIODIC) ? ny - 1 : j;
+            if (jp >= ny) jp = (p->bc_type[3] == ORC_PERIODIC) ? 0 : j;
+            gx[IDX(p, j, i)] = (rho[IDX(p, j, ip)] - rho[IDX(p, j, im)]) / 2.0;
+            gy[IDX(p, j, i)] = (rho[IDX(p, jp, i)] - rho[IDX(p, jm, i)]) / (2.0 * p->a);
+        }
+}
+
+/* Post-collision populations of every node (f -> f~). */
+void orc_collide(const orc_params *p, const double *f, double *ft)
+{
+    const size_t n = (size_t)p->nx * p->ny;
+    double *rho = malloc(n * sizeof(double));
+    double *gx = malloc(n * sizeof(double));
+    double *gy = malloc(n * sizeof(double));
+    double T[81], Ti[81];
+    orc_T(p->a, T);
+    orc_Tinv(p->a, Ti);
+    orc_density(p, f, rho);
+    orc_density_gradient(p, rho, gx, gy);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            double f9[9], o9[9];
+            gather9(p, f, i, j, f9);
+            collide_with(p, T, Ti, f9, gx[IDX(p, j, i)], gy[IDX(p, j, i)], o9);
+            for (int k = 0; k < 9; ++k)
+                ft[FIDX(p, k, j, i)] = o9[k];
+        }
+    free(rho);
+    free(gx);
+    free(gy);
+}
+
+/* Streaming by perfect shift, f_i(x, t+1) = f~_i(x - e_i, t), with periodic
+ * wrap or half-way bounce-back (moving-wall form of Sec. 5.2) where the
+ * source node lies outside the domain. */
+void orc_stream(const orc_params *p, const double *ft, double *f)
+{
+    const int nx = p->nx, ny = p->ny;
+    /* (feq_ibar - feq_i)(rho_w, u_w) for every face */
+    double dwall[4][9];
+    for (int face = 0; face < 4; ++face) {
+        double feq[9];
+        const double uwx = (p->bc_type[face] == ORC_MOVING_WALL) ? p->u_wall[face][0] : 0.0;
+        const double uwy = (p->bc_type[face] == ORC_MOVING_WALL) ? p->u_wall[face][1] : 0.0;
+        orc_feq(p, p->rho0, uwx, uwy, feq);
+        for (int k = 0; k < 9; ++k)
+            dwall[face][k] = feq[OPP[k]] - feq[k];
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < 9; ++k) {
+                int si = i - CX[k], sj = j - CY[k];
+                const int fx = (si < 0) ? 0 : (si >= nx) ? 1 : -1;
+                const int fy = (sj < 0) ? 2 : (sj >= ny) ? 3 : -1;
+                const int wx = (fx >= 0 && p->bc_type[fx] != ORC_PERIODIC) ? fx : -1;
+                const int wy = (fy >= 0 && p->bc_type[fy] != ORC_PERIODIC) ? fy : -1;
+                int face = -1;
+                if (wx >= 0 && wy >= 0)
+                    face = (p->bc_type[wx] == ORC_MOVING_WALL && p->bc_type[wy] != ORC_MOVING_WALL)
+                               ? wx
+                               : wy;
+                else if (wy >= 0)
+                    face = wy;
+                else if (wx >= 0)
+                    face = wx;
+                if (face >= 0) {
+                    f[FIDX(p, k, j, i)] = ft[FIDX(p, OPP[k], j, i)] - dwall[face][k];
+                } else {
+                    if (si < 0) si += nx;
+                    if (si >= nx) si -= nx;
+                    if (sj < 0) sj += ny;
+                    if (sj >= ny) sj -= ny;
+                    f[FIDX(p, k, j, i)] = ft[FIDX(p, k, sj, si)];
+                }
+            }
+}
+
+/* nsteps of collide + stream; f holds the populations at the current time
+ * level on entry and on exit.  work (9*nx*ny doubles) may be NULL. */
+void orc_run(const orc_params *p, double *f, double *work, long nsteps)
+{
+    const size_t n9 = (size_t)9 * p->nx * p->ny;
+    double *ft = work ? work : malloc(n9 * sizeof(double));
+    for (long s = 0; s < nsteps; ++s) {
+        orc_collide(p, f, ft);
+        orc_stream(p, ft, f);
+    }
+    if (!work)
+        free(ft);
+}
+
+void orc_moments(const orc_params *p, const double *f, double *rho, double *ux, double *uy)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            double f9[9], r, vx, vy;
+            gather9(p, f, i, j, f9);
+            orc_macro(p, f9, &r, &vx, &vy);
+            const size_t n = IDX(p, j, i);
+            if (rho) rho[n] = r;
+            if (ux) ux[n] = vx;
+            if (uy) uy[n] = vy;
+        }
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
