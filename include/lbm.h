@@ -1,0 +1,174 @@
+/*
+ * lbm.h -- C ABI of the MI355X library for the rectangular-lattice central
+ * moment lattice Boltzmann method of E. Yahia & K. N. Premnath, "Central
+ * Moment Lattice Boltzmann Method on a Rectangular Lattice" (arXiv
+ * 2103.02119).
+ *
+ * The library advances a D2Q9 lattice with grid aspect ratio a = dy/dx
+ * (Sec. 2.1) by the fused collide-and-stream step:
+ *   - RC-LBM (Sec. 4): relaxation of central moments toward the Maxwell-matched
+ *     central equilibria of Eq. 49, including the isotropy and Galilean
+ *     invariance corrections of Eq. 23-27 with the local strain rate of
+ *     Eq. 37-38 (the default);
+ *   - RNR-LBM (Sec. 3): the raw-moment special case;
+ *   - perfect-shift streaming with periodic faces, half-way bounce-back walls
+ *     and moving walls (Sec. 5.2, Eq. 57-59);
+ *   - the macroscopic fields rho = sum f, rho u = sum f e + F/2.
+ * Every step runs in hand-written HIP kernels for gfx950 on the caller's
+ * stream.  There is no CPU fallback: without a usable GPU every call that
+ * needs the device returns LBM_E_DEVICE.
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, dy = a; e_i = (cx_i, a cy_i) with the
+ *     ordering of Eq. 2: 0 (0,0), 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1),
+ *     5 (1,1), 6 (-1,1), 7 (-1,-1), 8 (1,-1) in (cx, cy).
+ *   - Node (i, j), 0 <= i < nx, 0 <= j < ny, sits at x = i, y = j a; a wall
+ *     lies half a node beyond the first/last row or column.
+ *   - Host scalar fields are double[ny][nx]; host populations are
+ *     double[9][ny][nx]; x fastest, C order.
+ *   - All functions return an int status (LBM_OK = 0, negative = error); no
+ *     exception or signal crosses the ABI.  lbm_last_error() describes the
+ *     last failure of a context.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,    /* invalid argument; nothing was changed */
+    LBM_E_NOMEM = -2,    /* a device or host allocation failed */
+    LBM_E_DEVICE = -3,   /* a HIP call failed or no GPU is usable */
+    LBM_E_UNSTABLE = -4, /* a reduction met NaN or Inf (the run has blown up) */
+    LBM_E_STATE = -5     /* the call needs a state the context is not in */
+};
+
+/* boundary type of a face */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_MOVING_WALL = 2 };
+/* face index into lbm_bc */
+enum { LBM_FACE_XMIN = 0, LBM_FACE_XMAX = 1, LBM_FACE_YMIN = 2, LBM_FACE_YMAX = 3 };
+/* collision model */
+enum { LBM_RC = 0, LBM_RNR = 1 };
+/* storage and arithmetic precision:
+ *   LBM_FP64      populations f stored and collided in FP64;
+ *   LBM_FP32_DEV  deviations g = f - w rho0 stored and collided in FP32
+ *                 (w = rest-state equilibrium weights); reductions in FP64;
+ *   LBM_FP64_DEV  the deviation algorithm in FP64 (a check of that algebra). */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP64_DEV = 2 };
+
+/* Boundary description.  x-min/x-max must both be periodic or both not; the
+ * same for y-min/y-max.  u_wall[face] = (Ux, Uy) is used by
+ * LBM_BC_MOVING_WALL faces (Sec. 5.2: f_i = f~_ibar - (feq_ibar - feq_i)(rho_w, u_w),
+ * rho_w = rho0).  A link that crosses two faces (a corner) uses the moving
+ * face if exactly one of them moves, else the y face. */
+typedef struct {
+    int type[4];
+    double u_wall[4][2];
+} lbm_bc;
+
+typedef struct {
+    double cs2;        /* squared speed of sound, 0 < cs2 < min(1, a^2) (rest weights
+                          positive); 0 selects min(1/3, 0.64 a^2) */
+    double force[2];   /* uniform body force (Fx, Fy), lattice units (Eq. 13) */
+    double rho0;       /* reference density: wall density and deviation origin; 0 => 1 */
+    int collision;     /* LBM_RC (default) or LBM_RNR */
+    int precision;     /* LBM_FP64 (default), LBM_FP32_DEV, LBM_FP64_DEV */
+    int corrections;   /* 1 (default): Eq. 23-27 corrections; 0: leave them out */
+    int rows_per_wave; /* launch shape override (rows marched by one wavefront);
+                          0 = automatic */
+    void *stream;      /* hipStream_t the library enqueues on; NULL = null stream */
+    void *f_a, *f_b;   /* optional caller-owned device buffers of f_bytes each
+                          (lbm_required_bytes); NULL => the library allocates */
+    size_t f_bytes;
+} lbm_opts;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fills *o with the defaults listed above. */
+void lbm_default_opts(lbm_opts *o);
+
+/* Device bytes of one population buffer (9 planes of ny rows, each row padded
+ * to a multiple of 64 values) for the given precision.
+ * Errors: LBM_E_INVAL for nx or ny < 3, a bad precision or a lattice whose
+ * plane exceeds 2^31 values. */
+int lbm_required_bytes(int nx, int ny, int precision, size_t *f_bytes);
+
+/* Creates a lattice of nx x ny nodes with aspect ratio r = a = dy/dx
+ * (Sec. 2.1) and relaxation rates rates[0..8] = omega_0..omega_8 (Eq. 5-6;
+ * the paper uses omega_4 = omega_5 = 1/tau, all others 1, with
+ * nu = cs2 (1/omega_4 - 1/2) and zeta = cs2 (1/omega_3 - 1/2), Eq. 32-33).
+ * The populations start at the rest equilibrium f = feq(rho0, 0).
+ * opts may be NULL (defaults).  Caller-owned buffers are borrowed, never
+ * freed, and must outlive the context.  Enqueues work on the stream and
+ * returns without waiting.
+ * Errors: LBM_E_INVAL when nx or ny < 3, r <= 0, cs2 not in (0, min(1, r^2)),
+ * an omega not in (0, 2), mismatched periodic faces, an unknown enum value or
+ * a caller buffer smaller than lbm_required_bytes; LBM_E_DEVICE without a
+ * usable GPU; LBM_E_NOMEM when allocation fails.  *out is NULL on error. */
+int lbm_create(int nx, int ny, double r, const double rates[9], const lbm_bc *bc,
+               const lbm_opts *opts, lbm_ctx **out);
+
+/* Sets f = feq(rho, u) at every node (product form of T^{-1} F(-u) applied to
+ * Eq. 49 without corrections; no non-equilibrium part).  rho, ux, uy are host
+ * double[ny][nx]; NULL means rho0 (rho) or 0 (ux, uy).  Synchronizes the
+ * stream.  Errors: LBM_E_DEVICE. */
+int lbm_set_fields(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy);
+
+/* Enqueues n >= 0 collide-and-stream steps on the stream (Sec. 3 / Sec. 4
+ * algorithm, one fused kernel per step) and returns without waiting.
+ * Errors: LBM_E_INVAL for n < 0; LBM_E_DEVICE if a launch fails. */
+int lbm_step(lbm_ctx *ctx, long n);
+
+/* Macroscopic fields at the current time level: rho = sum f,
+ * u = (sum f e + F/2) / rho (Sec. 3, "update hydrodynamic fields"), written
+ * to host double[ny][nx] arrays; any pointer may be NULL.  Synchronizes.
+ * Errors: LBM_E_DEVICE. */
+int lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
+
+/* Steady-state residual of the last step,
+ * R = sqrt(sum |u^n - u^{n-1}|^2) / sqrt(sum |u^n|^2), summed in FP64 over all
+ * nodes with a deterministic two-pass reduction.  Synchronizes.
+ * Errors: LBM_E_STATE before the first step (or after set_fields /
+ * set_populations); LBM_E_UNSTABLE if any velocity is NaN or Inf (*R is then
+ * NaN); LBM_E_DEVICE. */
+int lbm_residual(lbm_ctx *ctx, double *R);
+
+/* FP64 totals over all nodes at the current time level: out[0] = sum rho,
+ * out[1] = sum rho ux, out[2] = sum rho uy (momentum including the F/2
+ * shift).  Deterministic.  Synchronizes.  Errors: LBM_E_UNSTABLE (NaN/Inf),
+ * LBM_E_DEVICE. */
+int lbm_sums(lbm_ctx *ctx, double out[3]);
+
+/* Copies the populations f_i(x, t) of the current time level (after
+ * streaming, before collision) to / from host double[9][ny][nx].
+ * set_populations replaces the state and synchronizes; get synchronizes.
+ * Errors: LBM_E_DEVICE, LBM_E_NOMEM (staging buffer). */
+int lbm_get_populations(lbm_ctx *ctx, double *f);
+int lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/* Number of steps taken since creation (set_fields / set_populations do not
+ * reset it). */
+long lbm_steps_done(const lbm_ctx *ctx);
+
+/* Launch shape chosen for the step kernel: rows per wavefront and the number
+ * of workgroups.  Errors: LBM_E_INVAL for a NULL ctx. */
+int lbm_launch_shape(const lbm_ctx *ctx, int *rows_per_wave, int *workgroups);
+
+/* Text of the last error of ctx (or of the last failed lbm_create when ctx is
+ * NULL).  Never NULL; valid until the next call on the same context. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Releases the context and the buffers the library allocated (after
+ * synchronizing its stream).  NULL is a no-op.  Returns LBM_OK. */
+int lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -90,6 +90,7 @@ def lib():
             "orc_collide": [P, _D, _D],
             "orc_stream": [P, _D, _D],
             "orc_run": [P, _D, _D, ctypes.c_long],
+            "orc_step_node": [P, _D, ctypes.c_int, ctypes.c_int, _D],
             "orc_moments": [P, _D, _D, _D, _D],
             "orc_set_threads": [ctypes.c_int],
         }
@@ -207,6 +208,14 @@ def run(p, f, nsteps):
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     lib().orc_run(ctypes.byref(p), _ptr(f), None, int(nsteps))
     return f
+
+
+def step_node(p, f, i, j):
+    """Populations of node (i, j) after one step, from the whole field f."""
+    f = _f64(f)
+    out = np.zeros(9)
+    lib().orc_step_node(ctypes.byref(p), _ptr(f), int(i), int(j), _ptr(out))
+    return out
 
 
 def moments(p, f):

@@ -331,22 +331,35 @@ void orc_density(const orc_params *p, const double *f, double *rho)
         }
 }
 
+/* Neighbour used by the density gradient: across a periodic face it wraps,
+ * across a wall it is the node itself. */
+static int nb_x(const orc_params *p, int i, int d)
+{
+    const int n = i + d;
+    if (n < 0) return (p->bc_type[0] == ORC_PERIODIC) ? p->nx - 1 : i;
+    if (n >= p->nx) return (p->bc_type[1] == ORC_PERIODIC) ? 0 : i;
+    return n;
+}
+
+static int nb_y(const orc_params *p, int j, int d)
+{
+    const int n = j + d;
+    if (n < 0) return (p->bc_type[2] == ORC_PERIODIC) ? p->ny - 1 : j;
+    if (n >= p->ny) return (p->bc_type[3] == ORC_PERIODIC) ? 0 : j;
+    return n;
+}
+
 /* Central differences (the paper computes the density gradient "using a
- * central difference approach"); x spacing 1, y spacing a.  Across a
- * periodic face the neighbour wraps; across a wall it is the node itself. */
+ * central difference approach"); x spacing 1, y spacing a. */
 void orc_density_gradient(const orc_params *p, const double *rho, double *gx, double *gy)
 {
     const int nx = p->nx, ny = p->ny;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-            if (im < 0) im = (p->bc_type[0] == ORC_PERIODIC) ? nx - 1 : i;
-            if (ip >= nx) ip = (p->bc_type[1] == ORC_PERIODIC) ? 0 : i;
-            if (jm < 0) jm = (p->bc_type[2] == ORC_PERIODIC) ? ny - 1 : j;
-            if (jp >= ny) jp = (p->bc_type[3] == ORC_PERIODIC) ? 0 : j;
-            gx[IDX(p, j, i)] = (rho[IDX(p, j, ip)] - rho[IDX(p, j, im)]) / 2.0;
-            gy[IDX(p, j, i)] = (rho[IDX(p, jp, i)] - rho[IDX(p, jm, i)]) / (2.0 * p->a);
+            gx[IDX(p, j, i)] = (rho[IDX(p, j, nb_x(p, i, 1))] - rho[IDX(p, j, nb_x(p, i, -1))]) / 2.0;
+            gy[IDX(p, j, i)] =
+                (rho[IDX(p, nb_y(p, j, 1), i)] - rho[IDX(p, nb_y(p, j, -1), i)]) / (2.0 * p->a);
         }
 }
 
@@ -376,50 +389,95 @@ void orc_collide(const orc_params *p, const double *f, double *ft)
     free(gy);
 }
 
-/* Streaming by perfect shift, f_i(x, t+1) = f~_i(x - e_i, t), with periodic
- * wrap or half-way bounce-back (moving-wall form of Sec. 5.2) where the
- * source node lies outside the domain. */
-void orc_stream(const orc_params *p, const double *ft, double *f)
+/* Source of the link k that arrives at node (i, j) under perfect-shift
+ * streaming f_i(x, t+1) = f~_i(x - e_i, t).  Returns -1 and the (periodically
+ * wrapped) source node, or the index of the wall face the link crosses
+ * (half-way bounce-back).  A link crossing two wall faces takes the moving one
+ * if exactly one of them moves, else the y face. */
+static int link_source(const orc_params *p, int i, int j, int k, int *si_out, int *sj_out)
 {
     const int nx = p->nx, ny = p->ny;
-    /* (feq_ibar - feq_i)(rho_w, u_w) for every face */
-    double dwall[4][9];
+    int si = i - CX[k], sj = j - CY[k];
+    const int fx = (si < 0) ? 0 : (si >= nx) ? 1 : -1;
+    const int fy = (sj < 0) ? 2 : (sj >= ny) ? 3 : -1;
+    const int wx = (fx >= 0 && p->bc_type[fx] != ORC_PERIODIC) ? fx : -1;
+    const int wy = (fy >= 0 && p->bc_type[fy] != ORC_PERIODIC) ? fy : -1;
+    if (wx >= 0 && wy >= 0)
+        return (p->bc_type[wx] == ORC_MOVING_WALL && p->bc_type[wy] != ORC_MOVING_WALL) ? wx : wy;
+    if (wy >= 0) return wy;
+    if (wx >= 0) return wx;
+    if (si < 0) si += nx;
+    if (si >= nx) si -= nx;
+    if (sj < 0) sj += ny;
+    if (sj >= ny) sj -= ny;
+    *si_out = si;
+    *sj_out = sj;
+    return -1;
+}
+
+/* (feq_ibar - feq_i)(rho_w, u_w) of every face; rho_w = rho0, u_w = 0 for a
+ * stationary wall (then the difference vanishes). */
+static void wall_terms(const orc_params *p, double dwall[4][9])
+{
     for (int face = 0; face < 4; ++face) {
         double feq[9];
-        const double uwx = (p->bc_type[face] == ORC_MOVING_WALL) ? p->u_wall[face][0] : 0.0;
-        const double uwy = (p->bc_type[face] == ORC_MOVING_WALL) ? p->u_wall[face][1] : 0.0;
-        orc_feq(p, p->rho0, uwx, uwy, feq);
+        const int mv = p->bc_type[face] == ORC_MOVING_WALL;
+        orc_feq(p, p->rho0, mv ? p->u_wall[face][0] : 0.0, mv ? p->u_wall[face][1] : 0.0, feq);
         for (int k = 0; k < 9; ++k)
             dwall[face][k] = feq[OPP[k]] - feq[k];
     }
+}
+
+/* Streaming by perfect shift with periodic wrap or half-way bounce-back
+ * (moving-wall form of Sec. 5.2) where the source node lies outside. */
+void orc_stream(const orc_params *p, const double *ft, double *f)
+{
+    double dwall[4][9];
+    wall_terms(p, dwall);
 #pragma omp parallel for schedule(static)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i)
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i)
             for (int k = 0; k < 9; ++k) {
-                int si = i - CX[k], sj = j - CY[k];
-                const int fx = (si < 0) ? 0 : (si >= nx) ? 1 : -1;
-                const int fy = (sj < 0) ? 2 : (sj >= ny) ? 3 : -1;
-                const int wx = (fx >= 0 && p->bc_type[fx] != ORC_PERIODIC) ? fx : -1;
-                const int wy = (fy >= 0 && p->bc_type[fy] != ORC_PERIODIC) ? fy : -1;
-                int face = -1;
-                if (wx >= 0 && wy >= 0)
-                    face = (p->bc_type[wx] == ORC_MOVING_WALL && p->bc_type[wy] != ORC_MOVING_WALL)
-                               ? wx
-                               : wy;
-                else if (wy >= 0)
-                    face = wy;
-                else if (wx >= 0)
-                    face = wx;
-                if (face >= 0) {
+                int si = 0, sj = 0;
+                const int face = link_source(p, i, j, k, &si, &sj);
+                if (face >= 0)
                     f[FIDX(p, k, j, i)] = ft[FIDX(p, OPP[k], j, i)] - dwall[face][k];
-                } else {
-                    if (si < 0) si += nx;
-                    if (si >= nx) si -= nx;
-                    if (sj < 0) sj += ny;
-                    if (sj >= ny) sj -= ny;
+                else
                     f[FIDX(p, k, j, i)] = ft[FIDX(p, k, sj, si)];
-                }
             }
+}
+
+static double node_density(const orc_params *p, const double *f, int i, int j)
+{
+    double r = 0.0;
+    for (int k = 0; k < 9; ++k)
+        r += f[FIDX(p, k, j, i)];
+    return r;
+}
+
+/* One node's populations after one collide + stream step, evaluated from the
+ * whole pre-step field f without touching any other node's output: the
+ * sources of its nine links are collided one by one (each with its own
+ * central-difference density gradient) and streamed as in orc_stream. */
+void orc_step_node(const orc_params *p, const double *f, int i, int j, double *out9)
+{
+    double T[81], Ti[81], dwall[4][9];
+    orc_T(p->a, T);
+    orc_Tinv(p->a, Ti);
+    wall_terms(p, dwall);
+    for (int k = 0; k < 9; ++k) {
+        int si = i, sj = j;
+        const int face = link_source(p, i, j, k, &si, &sj);
+        const int comp = face >= 0 ? OPP[k] : k;
+        double f9[9], o9[9];
+        gather9(p, f, si, sj, f9);
+        const double gx = (node_density(p, f, nb_x(p, si, 1), sj) -
+                           node_density(p, f, nb_x(p, si, -1), sj)) / 2.0;
+        const double gy = (node_density(p, f, si, nb_y(p, sj, 1)) -
+                           node_density(p, f, si, nb_y(p, sj, -1))) / (2.0 * p->a);
+        collide_with(p, T, Ti, f9, gx, gy, o9);
+        out9[k] = o9[comp] - (face >= 0 ? dwall[face][k] : 0.0);
+    }
 }
 
 /* nsteps of collide + stream; f holds the populations at the current time

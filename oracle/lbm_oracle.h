@@ -65,6 +65,7 @@ void orc_density(const orc_params *p, const double *f, double *rho);
 void orc_density_gradient(const orc_params *p, const double *rho, double *gx, double *gy);
 void orc_collide(const orc_params *p, const double *f, double *ft);
 void orc_stream(const orc_params *p, const double *ft, double *f);
+void orc_step_node(const orc_params *p, const double *f, int i, int j, double *out9);
 void orc_run(const orc_params *p, double *f, double *work, long nsteps);
 void orc_moments(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
 

@@ -1,0 +1,458 @@
+// Host side of the C ABI declared in include/lbm.h: argument validation,
+// model constants, buffer management, state tracking and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local char g_create_error[512] = "no error";
+
+// Storage form of a population buffer.
+enum Form { kEmpty = 0, kPre = 1, kPost = 2 };
+
+}  // namespace
+
+struct lbm_ctx {
+    int nx, ny;
+    double a;
+    double rates[9];
+    lbm_bc bc;
+    lbm_opts opts;
+    int prec, coll;
+    hipStream_t stream;
+    Geometry G;
+    Consts<double> Kd;
+    Consts<float> Kf;
+    HostSide H;
+    bool higher_unit;
+    size_t f_bytes;
+    void *f[2];
+    bool owns[2];
+    int cur;          // buffer with the current state
+    int form[2];      // Form of each buffer's contents
+    int prev_valid;   // the other buffer holds the state one step earlier
+    double *d_partials;  // reduction partials + results
+    double *d_stage;     // FP64 staging for host transfers (lazy)
+    size_t stage_bytes;
+    long steps;
+    char err[512];
+};
+
+static int fail_ctx(lbm_ctx *ctx, int code, const char *fmt, ...) {
+    char *buf = ctx ? ctx->err : g_create_error;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                          \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail_ctx((ctx), e_ == hipErrorOutOfMemory ? LBM_E_NOMEM : LBM_E_DEVICE, \
+                            "%s failed: %s", #call, hipGetErrorString(e_));            \
+    } while (0)
+
+static int pitch_of(int nx) { return (nx + kWave - 1) / kWave * kWave; }
+
+static size_t value_bytes(int prec) { return prec == kFP32Dev ? sizeof(float) : sizeof(double); }
+
+extern "C" void lbm_default_opts(lbm_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->cs2 = 0.0;
+    o->rho0 = 1.0;
+    o->collision = LBM_RC;
+    o->precision = LBM_FP64;
+    o->corrections = 1;
+}
+
+extern "C" int lbm_required_bytes(int nx, int ny, int precision, size_t *f_bytes) {
+    if (!f_bytes) return fail_ctx(nullptr, LBM_E_INVAL, "f_bytes is NULL");
+    if (nx < 3 || ny < 3) return fail_ctx(nullptr, LBM_E_INVAL, "nx and ny must be >= 3");
+    if (precision < LBM_FP64 || precision > LBM_FP64_DEV)
+        return fail_ctx(nullptr, LBM_E_INVAL, "unknown precision %d", precision);
+    const long long plane = static_cast<long long>(pitch_of(nx)) * ny;
+    if (plane > 0x7fffffffLL)
+        return fail_ctx(nullptr, LBM_E_INVAL, "lattice too large: %lld values per plane", plane);
+    *f_bytes = static_cast<size_t>(9) * plane * value_bytes(precision);
+    return LBM_OK;
+}
+
+// Equilibrium in product form (the library's own, used for the rest weights
+// and the moving-wall terms): feq_k = rho Px(cx) Py(cy).
+static double feq_host(int k, double rho, double ux, double uy, double s, double a) {
+    const int cx = cx_of(k), cy = cy_of(k);
+    const double px = cx == 0 ? 1.0 - s - ux * ux : 0.5 * (s + ux * ux + cx * ux);
+    const double py = cy == 0 ? 1.0 - (s + uy * uy) / (a * a)
+                              : 0.5 * (s + uy * uy + cy * a * uy) / (a * a);
+    return rho * px * py;
+}
+
+template <typename R>
+static void fill_consts(const lbm_ctx *c, Consts<R> &K) {
+    const double a = c->a, s = c->opts.cs2;
+    const double *w = c->rates;
+    K.a = R(a);
+    K.inv_a = R(1.0 / a);
+    K.a2 = R(a * a);
+    K.inv_a2 = R(1.0 / (a * a));
+    K.half_inv_a = R(0.5 / a);
+    K.s = R(s);
+    K.s2 = R(s * s);
+    K.rr = R(c->prec == kFP64 ? 0.0 : c->opts.rho0);
+    K.Fx = R(c->opts.force[0]);
+    K.Fy = R(c->opts.force[1]);
+    K.hFx = R(0.5 * c->opts.force[0]);
+    K.hFy = R(0.5 * c->opts.force[1]);
+    for (int j = 0; j < 9; ++j) {
+        K.w[j] = R(w[j]);
+        K.om[j] = R(1.0 - w[j]);
+        K.sw[j] = R(1.0 - 0.5 * w[j]);
+    }
+    K.k3 = R(1.0 / w[3] - 0.5);
+    K.k4 = R(1.0 / w[4] - 0.5);
+    // Eq. 40 divided by rho, without the velocity terms
+    K.b1c = R(-2.0 * s / w[3] - (-3.0 * s + 1.0) / 2.0);
+    K.b2c = R(-2.0 * s / w[3] - (-3.0 * s + a * a) / 2.0);
+    K.c1c = R(-2.0 * s / w[4] - (-3.0 * s + 1.0) / 2.0);
+    K.c2c = R(2.0 * s / w[4] - (3.0 * s - a * a) / 2.0);
+    K.e1 = R((3.0 * s - 1.0) / 2.0);
+    K.e2 = R((3.0 * s - a * a) / 2.0);
+    K.q1 = R(1.0 - 3.0 * s);
+    K.q2 = R(a * a - 3.0 * s);
+    for (int f = 0; f < 4; ++f) {
+        const bool mv = c->bc.type[f] == LBM_BC_MOVING_WALL;
+        const double ux = mv ? c->bc.u_wall[f][0] : 0.0, uy = mv ? c->bc.u_wall[f][1] : 0.0;
+        for (int k = 0; k < 9; ++k)
+            K.dwall[f][k] = R(feq_host(opp_of(k), c->opts.rho0, ux, uy, s, a) -
+                              feq_host(k, c->opts.rho0, ux, uy, s, a));
+    }
+}
+
+static void choose_launch(lbm_ctx *c) {
+    Geometry &G = c->G;
+    G.nseg = (c->nx + kWave - 1) / kWave;
+    int rows = c->opts.rows_per_wave;
+    if (rows <= 0) {
+        // aim at ~8192 wavefronts (32 per CU on 256 CUs), 4..32 rows each
+        const long long want = (static_cast<long long>(c->ny) * G.nseg + 8191) / 8192;
+        rows = 4;
+        while (rows < want && rows < 32) rows *= 2;
+    }
+    if (rows > kMaxRows) rows = kMaxRows;
+    if (rows > c->ny) rows = c->ny;
+    G.rows = rows;
+    G.nchunk = (c->ny + rows - 1) / rows;
+    G.ntile = G.nseg * G.nchunk;
+    G.nblocks = (G.ntile + kWavesPerBlock - 1) / kWavesPerBlock;
+    G.xcd_remap = (G.nblocks % 8 == 0) ? 1 : 0;
+}
+
+static int validate(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
+                    const lbm_opts *o) {
+    if (nx < 3 || ny < 3) return fail_ctx(nullptr, LBM_E_INVAL, "nx and ny must be >= 3");
+    if (!(r > 0.0) || !isfinite(r)) return fail_ctx(nullptr, LBM_E_INVAL, "r must be > 0");
+    if (!rates) return fail_ctx(nullptr, LBM_E_INVAL, "rates is NULL");
+    for (int j = 0; j < 9; ++j)
+        if (!(rates[j] > 0.0 && rates[j] < 2.0))
+            return fail_ctx(nullptr, LBM_E_INVAL, "rates[%d] = %g is not in (0, 2)", j, rates[j]);
+    const double lim = fmin(1.0, r * r);
+    if (!(o->cs2 > 0.0 && o->cs2 < lim))
+        return fail_ctx(nullptr, LBM_E_INVAL, "cs2 = %g is not in (0, min(1, r^2) = %g)", o->cs2,
+                        lim);
+    if (!bc) return fail_ctx(nullptr, LBM_E_INVAL, "bc is NULL");
+    for (int f = 0; f < 4; ++f)
+        if (bc->type[f] < LBM_BC_PERIODIC || bc->type[f] > LBM_BC_MOVING_WALL)
+            return fail_ctx(nullptr, LBM_E_INVAL, "unknown boundary type %d on face %d",
+                            bc->type[f], f);
+    if ((bc->type[0] == LBM_BC_PERIODIC) != (bc->type[1] == LBM_BC_PERIODIC) ||
+        (bc->type[2] == LBM_BC_PERIODIC) != (bc->type[3] == LBM_BC_PERIODIC))
+        return fail_ctx(nullptr, LBM_E_INVAL, "opposite faces must both be periodic or both not");
+    if (o->collision != LBM_RC && o->collision != LBM_RNR)
+        return fail_ctx(nullptr, LBM_E_INVAL, "unknown collision %d", o->collision);
+    if (o->precision < LBM_FP64 || o->precision > LBM_FP64_DEV)
+        return fail_ctx(nullptr, LBM_E_INVAL, "unknown precision %d", o->precision);
+    if (!(o->rho0 > 0.0)) return fail_ctx(nullptr, LBM_E_INVAL, "rho0 must be > 0");
+    if (!isfinite(o->force[0]) || !isfinite(o->force[1]))
+        return fail_ctx(nullptr, LBM_E_INVAL, "force must be finite");
+    if (o->rows_per_wave < 0 || o->rows_per_wave > kMaxRows)
+        return fail_ctx(nullptr, LBM_E_INVAL, "rows_per_wave must be in [0, %d]", kMaxRows);
+    if ((o->f_a == nullptr) != (o->f_b == nullptr))
+        return fail_ctx(nullptr, LBM_E_INVAL, "give both f_a and f_b or neither");
+    return LBM_OK;
+}
+
+static int ensure_stage(lbm_ctx *c, size_t bytes) {
+    if (c->stage_bytes >= bytes) return LBM_OK;
+    if (c->d_stage) {
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        HIP_OR_FAIL(c, hipFree(c->d_stage));
+        c->d_stage = nullptr;
+        c->stage_bytes = 0;
+    }
+    HIP_OR_FAIL(c, hipMalloc(&c->d_stage, bytes));
+    c->stage_bytes = bytes;
+    return LBM_OK;
+}
+
+static int init_fields_device(lbm_ctx *c, const double *drho, const double *dux,
+                              const double *duy) {
+    HIP_OR_FAIL(c, launch_init_feq(c->prec, c->f[c->cur], drho, dux, duy, c->G, c->H, c->stream));
+    c->form[c->cur] = kPre;
+    c->form[1 - c->cur] = kEmpty;
+    c->prev_valid = 0;
+    return LBM_OK;
+}
+
+extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const lbm_bc *bc,
+                          const lbm_opts *opts, lbm_ctx **out) {
+    if (!out) return fail_ctx(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    lbm_opts o;
+    if (opts) o = *opts; else lbm_default_opts(&o);
+    if (o.rho0 == 0.0) o.rho0 = 1.0;
+    if (o.cs2 == 0.0) o.cs2 = fmin(1.0 / 3.0, 0.64 * r * r);
+    int rc = validate(nx, ny, r, rates, bc, &o);
+    if (rc != LBM_OK) return rc;
+    size_t need = 0;
+    rc = lbm_required_bytes(nx, ny, o.precision, &need);
+    if (rc != LBM_OK) return rc;
+    if (o.f_a && o.f_bytes < need)
+        return fail_ctx(nullptr, LBM_E_INVAL, "caller buffers hold %zu bytes, %zu needed",
+                        o.f_bytes, need);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail_ctx(nullptr, LBM_E_DEVICE, "no usable GPU");
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail_ctx(nullptr, LBM_E_NOMEM, "out of host memory");
+    c->nx = nx;
+    c->ny = ny;
+    c->a = r;
+    memcpy(c->rates, rates, sizeof(c->rates));
+    c->bc = *bc;
+    c->opts = o;
+    c->prec = o.precision;
+    c->coll = o.collision;
+    c->stream = static_cast<hipStream_t>(o.stream);
+    c->higher_unit = rates[6] == 1.0 && rates[7] == 1.0 && rates[8] == 1.0;
+    snprintf(c->err, sizeof(c->err), "no error");
+
+    Geometry &G = c->G;
+    G.nx = nx;
+    G.ny = ny;
+    G.pitch = pitch_of(nx);
+    G.plane = static_cast<long long>(G.pitch) * ny;
+    for (int f = 0; f < 4; ++f) G.bc[f] = bc->type[f];
+    G.corr = o.corrections ? 1 : 0;
+    choose_launch(c);
+    fill_consts(c, c->Kd);
+    fill_consts(c, c->Kf);
+    for (int k = 0; k < 9; ++k) c->H.wrest[k] = feq_host(k, 1.0, 0.0, 0.0, o.cs2, r);
+    c->H.rho0 = o.rho0;
+    c->H.a = r;
+    c->H.s = o.cs2;
+    c->H.Fx = o.force[0];
+    c->H.Fy = o.force[1];
+    c->H.dev = c->prec == kFP64 ? 0 : 1;
+    c->f_bytes = need;
+
+    int status = LBM_OK;
+    if (o.f_a) {
+        c->f[0] = o.f_a;
+        c->f[1] = o.f_b;
+    } else {
+        for (int i = 0; i < 2 && status == LBM_OK; ++i) {
+            hipError_t e = hipMalloc(&c->f[i], need);
+            if (e != hipSuccess) {
+                c->f[i] = nullptr;
+                status = fail_ctx(nullptr, e == hipErrorOutOfMemory ? LBM_E_NOMEM : LBM_E_DEVICE,
+                                  "hipMalloc of %zu bytes failed: %s", need, hipGetErrorString(e));
+            } else {
+                c->owns[i] = true;
+            }
+        }
+    }
+    if (status == LBM_OK) {
+        hipError_t e = hipMalloc(&c->d_partials, (4 * kMaxPartials + 8) * sizeof(double));
+        if (e != hipSuccess) {
+            c->d_partials = nullptr;
+            status = fail_ctx(nullptr, LBM_E_DEVICE, "hipMalloc of partials failed: %s",
+                              hipGetErrorString(e));
+        }
+    }
+    if (status == LBM_OK) {
+        c->cur = 0;
+        status = init_fields_device(c, nullptr, nullptr, nullptr);
+        if (status != LBM_OK) snprintf(g_create_error, sizeof(g_create_error), "%s", c->err);
+    }
+    if (status != LBM_OK) {
+        lbm_destroy(c);
+        return status;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_fields(lbm_ctx *c, const double *rho, const double *ux, const double *uy) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const size_t n = static_cast<size_t>(c->nx) * c->ny;
+    int rc = ensure_stage(c, 3 * n * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    double *d[3] = {nullptr, nullptr, nullptr};
+    const double *h[3] = {rho, ux, uy};
+    for (int i = 0; i < 3; ++i)
+        if (h[i]) {
+            d[i] = c->d_stage + i * n;
+            HIP_OR_FAIL(c, hipMemcpyAsync(d[i], h[i], n * sizeof(double), hipMemcpyHostToDevice,
+                                          c->stream));
+        }
+    rc = init_fields_device(c, d[0], d[1], d[2]);
+    if (rc != LBM_OK) return rc;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_ctx *c, long n) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (n < 0) return fail_ctx(c, LBM_E_INVAL, "n must be >= 0");
+    for (long i = 0; i < n; ++i) {
+        const int src = c->cur, dst = 1 - c->cur;
+        const bool pull = c->form[src] == kPost;
+        hipError_t e = launch_step(c->prec, c->coll, pull, c->higher_unit, c->f[src], c->f[dst],
+                                   c->G, c->Kd, c->Kf, c->stream);
+        if (e != hipSuccess)
+            return fail_ctx(c, LBM_E_DEVICE, "step kernel launch failed: %s", hipGetErrorString(e));
+        c->form[dst] = kPost;
+        c->cur = dst;
+        c->prev_valid = 1;
+        ++c->steps;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const size_t n = static_cast<size_t>(c->nx) * c->ny;
+    int rc = ensure_stage(c, 3 * n * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    double *d = c->d_stage;
+    HIP_OR_FAIL(c, launch_moments(c->prec, c->form[c->cur] == kPost, c->f[c->cur], d, d + n,
+                                  d + 2 * n, c->G, c->Kd, c->Kf, c->H, c->stream));
+    double *h[3] = {rho, ux, uy};
+    for (int i = 0; i < 3; ++i)
+        if (h[i])
+            HIP_OR_FAIL(c, hipMemcpyAsync(h[i], d + i * n, n * sizeof(double),
+                                          hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+static int fetch_result(lbm_ctx *c, double out[4]) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(out, c->d_partials + 4 * kMaxPartials, 4 * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+extern "C" int lbm_sums(lbm_ctx *c, double out[3]) {
+    if (!c || !out) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
+    HIP_OR_FAIL(c, launch_sums(c->prec, c->form[c->cur] == kPost, c->f[c->cur], c->d_partials,
+                               c->d_partials + 4 * kMaxPartials, c->G, c->Kd, c->Kf, c->H,
+                               c->stream));
+    double r[4];
+    int rc = fetch_result(c, r);
+    if (rc != LBM_OK) return rc;
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = r[2];
+    if (r[3] != 0.0 || !isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]))
+        return fail_ctx(c, LBM_E_UNSTABLE, "non-finite density or velocity");
+    return LBM_OK;
+}
+
+extern "C" int lbm_residual(lbm_ctx *c, double *R) {
+    if (!c || !R) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
+    if (!c->prev_valid || c->form[1 - c->cur] == kEmpty)
+        return fail_ctx(c, LBM_E_STATE, "no step taken since the state was set");
+    const int p = 1 - c->cur;
+    HIP_OR_FAIL(c, launch_residual(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
+                                   c->form[p] == kPost, c->f[p], c->d_partials,
+                                   c->d_partials + 4 * kMaxPartials, c->G, c->Kd, c->Kf, c->H,
+                                   c->stream));
+    double r[4];
+    int rc = fetch_result(c, r);
+    if (rc != LBM_OK) return rc;
+    if (r[3] != 0.0 || !isfinite(r[0]) || !isfinite(r[1])) {
+        *R = NAN;
+        return fail_ctx(c, LBM_E_UNSTABLE, "non-finite velocity");
+    }
+    *R = r[1] > 0.0 ? sqrt(r[0]) / sqrt(r[1]) : (r[0] > 0.0 ? INFINITY : 0.0);
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_populations(lbm_ctx *c, double *f) {
+    if (!c || !f) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
+    const size_t n9 = static_cast<size_t>(9) * c->nx * c->ny;
+    int rc = ensure_stage(c, n9 * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    HIP_OR_FAIL(c, launch_get_populations(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
+                                          c->d_stage, c->G, c->Kd, c->Kf, c->H, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(f, c->d_stage, n9 * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_populations(lbm_ctx *c, const double *f) {
+    if (!c || !f) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
+    const size_t n9 = static_cast<size_t>(9) * c->nx * c->ny;
+    int rc = ensure_stage(c, n9 * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->d_stage, f, n9 * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+    HIP_OR_FAIL(c, launch_set_populations(c->prec, c->f[c->cur], c->d_stage, c->G, c->H,
+                                          c->stream));
+    c->form[c->cur] = kPre;
+    c->form[1 - c->cur] = kEmpty;
+    c->prev_valid = 0;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+extern "C" long lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : 0; }
+
+extern "C" int lbm_launch_shape(const lbm_ctx *c, int *rows_per_wave, int *workgroups) {
+    if (!c) return LBM_E_INVAL;
+    if (rows_per_wave) *rows_per_wave = c->G.rows;
+    if (workgroups) *workgroups = c->G.nblocks;
+    return LBM_OK;
+}
+
+extern "C" const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err : g_create_error; }
+
+extern "C" int lbm_destroy(lbm_ctx *c) {
+    if (!c) return LBM_OK;
+    if (c->stream || c->f[0]) (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < 2; ++i)
+        if (c->owns[i] && c->f[i]) (void)hipFree(c->f[i]);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_stage) (void)hipFree(c->d_stage);
+    delete c;
+    return LBM_OK;
+}

@@ -1,0 +1,97 @@
+// Internal declarations shared by the HIP kernels and the host side of the
+// C ABI (include/lbm.h).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kWavesPerBlock = 4;   // independent wavefronts per workgroup
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMaxRows = 64;        // rows marched by one wavefront (halo pass width)
+constexpr int kReduceBlock = 256;
+constexpr int kMaxPartials = 4096;  // per-block partial sums of the reductions
+
+enum Prec { kFP64 = 0, kFP32Dev = 1, kFP64Dev = 2 };
+enum Face { kXmin = 0, kXmax = 1, kYmin = 2, kYmax = 3 };
+enum Bc { kPeriodic = 0, kWall = 1, kMovingWall = 2 };
+enum Coll { kRC = 0, kRNR = 1 };
+
+// (cx, cy) of direction k in the ordering of Eq. 2; e = (cx, a cy).
+__host__ __device__ constexpr int cx_of(int k) {
+    return (k == 1 || k == 5 || k == 8) ? 1 : ((k == 3 || k == 6 || k == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy_of(int k) {
+    return (k == 2 || k == 5 || k == 6) ? 1 : ((k == 4 || k == 7 || k == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp_of(int k) {
+    return k == 0 ? 0 : k == 1 ? 3 : k == 2 ? 4 : k == 3 ? 1 : k == 4 ? 2
+         : k == 5 ? 7 : k == 6 ? 8 : k == 7 ? 5 : 6;
+}
+
+// Lattice geometry and launch tiling (uniform kernel argument).
+struct Geometry {
+    int nx, ny, pitch;       // pitch: row stride in values (multiple of 64)
+    int nseg;                // 64-column segments per row
+    int rows;                // rows marched by one wavefront
+    int nchunk;              // row chunks
+    int ntile;               // nseg * nchunk wavefront tiles
+    int nblocks;             // workgroups of the step kernel
+    int xcd_remap;           // 1: contiguous tiles per XCD (nblocks % 8 == 0)
+    int bc[4];               // Bc per face
+    int corr;                // 1: Eq. 23-27 corrections on
+    long long plane;         // pitch * ny
+};
+
+// Model constants in the arithmetic type R of a kernel.
+template <typename R>
+struct Consts {
+    R a, inv_a, a2, inv_a2, half_inv_a;
+    R s, s2;                 // cs2, cs2^2
+    R rr;                    // deviation origin rho0 (0 when f itself is stored)
+    R Fx, Fy, hFx, hFy;      // force and half force
+    R w[9];                  // omega_j
+    R om[9];                 // 1 - omega_j
+    R sw[9];                 // 1 - omega_j / 2
+    R k3, k4;                // 1/omega_3 - 1/2, 1/omega_4 - 1/2
+    R b1c, b2c, c1c, c2c;    // u-independent parts of B1/rho, B2/rho, C1/rho, C2/rho (Eq. 40)
+    R e1, e2;                // (3 cs2 - 1)/2, (3 cs2 - a^2)/2 (B3/ux, B4/uy of Eq. 40)
+    R q1, q2;                // 1 - 3 cs2, a^2 - 3 cs2 (Eq. 23-24)
+    R dwall[4][9];           // (feq_opp(k) - feq_k)(rho0, u_wall[face]) per face
+};
+
+// Per-context constants for the conversion kernels (always FP64).
+struct HostSide {
+    double wrest[9];         // rest weights w_k = feq_k(1, 0)
+    double rho0, a, s, Fx, Fy;
+    int dev;                 // 1: storage holds f - w rho0
+};
+
+// ---- launchers implemented in lbm_kernels.hip (return hipError_t) ----
+hipError_t launch_step(int prec, int coll, bool pull, bool higher_unit, const void *src, void *dst,
+                       const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
+                       hipStream_t st);
+hipError_t launch_init_feq(int prec, void *dst, const double *rho, const double *ux,
+                           const double *uy, const Geometry &G, const HostSide &H, hipStream_t st);
+hipError_t launch_set_populations(int prec, void *dst, const double *f, const Geometry &G,
+                                  const HostSide &H, hipStream_t st);
+// pull: 1 if the buffer holds post-collision values of the previous step
+hipError_t launch_get_populations(int prec, bool pull, const void *src, double *f,
+                                  const Geometry &G, const Consts<double> &Kd,
+                                  const Consts<float> &Kf, const HostSide &H, hipStream_t st);
+hipError_t launch_moments(int prec, bool pull, const void *src, double *rho, double *ux,
+                          double *uy, const Geometry &G, const Consts<double> &Kd,
+                          const Consts<float> &Kf, const HostSide &H, hipStream_t st);
+// out[0..2] = sum rho, sum rho ux, sum rho uy, out[3] = 1 if NaN/Inf met
+hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, double *out,
+                       const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
+                       const HostSide &H, hipStream_t st);
+// out[0] = sum |u_cur - u_prev|^2, out[1] = sum |u_cur|^2, out[3] = NaN/Inf flag
+hipError_t launch_residual(int prec, bool pull_cur, const void *cur, bool pull_prev,
+                           const void *prev, double *partials, double *out, const Geometry &G,
+                           const Consts<double> &Kd, const Consts<float> &Kf, const HostSide &H,
+                           hipStream_t st);
+
+}  // namespace lbm

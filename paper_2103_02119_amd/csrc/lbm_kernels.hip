@@ -1,0 +1,727 @@
+// HIP kernels (gfx950) of the rectangular-lattice central-moment LBM
+// (Yahia & Premnath, arXiv 2103.02119).
+//
+// Step kernel layout
+//   * Populations live in 9 SoA planes [k][ny][pitch] (pitch = nx rounded up
+//     to 64 values), x fastest, so a wavefront's 64 lanes read and write one
+//     contiguous 64-value row segment per plane.
+//   * Pull streaming: the step at time t reads the post-collision values of
+//     t-1 shifted by (cx, cy) nodes (perfect shift, Sec. 3 / Sec. 4), so all
+//     stores are aligned and coalesced.  A buffer that holds pre-collision
+//     values (after set_fields / set_populations) is read in place instead.
+//   * Each wavefront owns 64 columns x `rows` rows and marches up the rows,
+//     keeping the populations of rows j and j+1 in registers.  The density
+//     gradient (the only non-local input of the collision, Sec. 2.3) needs
+//     rho of the 4 neighbours at the same time level: the row below and above
+//     come from the marching window, the left/right neighbours from a
+//     wavefront shuffle, and the two columns beyond the segment from a halo
+//     pass done once per wavefront (one halo node per lane).
+//   * The collision is done in component form (the paper's advice, Sec. 3):
+//     1-D moment transforms along x then y, the relaxation in the paper's
+//     moment basis, then the inverse transforms.  No matrix is formed.
+//   * FP32 deviation mode stores g = f - w rho0 and carries every moment as a
+//     deviation from the rest state so that no O(1) quantity is subtracted
+//     from another in FP32.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------ small helpers
+
+__device__ __forceinline__ float readlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<unsigned int>(lo));
+}
+
+template <typename R>
+__device__ __forceinline__ R sum9(const R (&f)[9]) {
+    // same grouping as the x-sums of the collision: (0,1,3), (2,5,6), (4,8,7)
+    return ((f[0] + f[1] + f[3]) + (f[2] + f[5] + f[6])) + (f[4] + f[8] + f[7]);
+}
+
+struct RowInfo {
+    int j, jb, jt;   // row, source row of cy = +1 links, source row of cy = -1 links
+    bool wb, wt;     // source of cy = +1 / cy = -1 links lies across a wall
+};
+struct ColInfo {
+    int x, xl, xr;   // column, source column of cx = +1 links, of cx = -1 links
+    bool wl, wr;
+};
+
+__device__ __forceinline__ RowInfo row_info(int j, const Geometry &G) {
+    RowInfo r;
+    const bool cb = (j == 0), ct = (j == G.ny - 1);
+    r.j = j;
+    r.jb = cb ? G.ny - 1 : j - 1;
+    r.jt = ct ? 0 : j + 1;
+    r.wb = cb && G.bc[kYmin] != kPeriodic;
+    r.wt = ct && G.bc[kYmax] != kPeriodic;
+    return r;
+}
+__device__ __forceinline__ ColInfo col_info(int x, const Geometry &G) {
+    ColInfo c;
+    const bool cl = (x == 0), cr = (x == G.nx - 1);
+    c.x = x;
+    c.xl = cl ? G.nx - 1 : x - 1;
+    c.xr = cr ? 0 : x + 1;
+    c.wl = cl && G.bc[kXmin] != kPeriodic;
+    c.wr = cr && G.bc[kXmax] != kPeriodic;
+    return c;
+}
+
+// Pre-collision populations of node (x, j): pulled with periodic wrap and
+// half-way bounce-back, f_k = f~_opp(k)(x) - (feq_opp(k) - feq_k)(rho0, u_w),
+// where the source node lies beyond a wall (Sec. 5.2).  Without PULL the
+// buffer already holds pre-collision values and is read in place.
+template <typename S, typename R, bool PULL>
+__device__ __forceinline__ void load_node(const S *__restrict__ src, const Geometry &G,
+                                          const Consts<R> &K, const RowInfo &r,
+                                          const ColInfo &c, R (&f)[9]) {
+    const long long P = G.plane;
+    const long long own = static_cast<long long>(r.j) * G.pitch + c.x;
+    if (!PULL) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = static_cast<R>(src[k * P + own]);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = cx_of(k), cy = cy_of(k);
+        const int row = cy > 0 ? r.jb : (cy < 0 ? r.jt : r.j);
+        const int col = cx > 0 ? c.xl : (cx < 0 ? c.xr : c.x);
+        const bool wy = cy > 0 ? r.wb : (cy < 0 ? r.wt : false);
+        const bool wx = cx > 0 ? c.wl : (cx < 0 ? c.wr : false);
+        if (wx || wy) {
+            const int xf = cx > 0 ? kXmin : kXmax;
+            const int yf = cy > 0 ? kYmin : kYmax;
+            const bool use_x =
+                wx && (!wy || (G.bc[xf] == kMovingWall && G.bc[yf] != kMovingWall));
+            const R d = use_x ? K.dwall[xf][k] : K.dwall[yf][k];
+            f[k] = static_cast<R>(src[opp_of(k) * P + own]) - d;
+        } else {
+            f[k] = static_cast<R>(src[k * P + static_cast<long long>(row) * G.pitch + col]);
+        }
+    }
+}
+
+// Interior node (1 <= x <= nx-2, 1 <= j <= ny-2): no wrap, no wall.
+template <typename S, typename R, bool PULL>
+__device__ __forceinline__ void load_interior(const S *__restrict__ src, const Geometry &G,
+                                              int j, int x, R (&f)[9]) {
+    const long long P = G.plane;
+    const S *q = src + static_cast<long long>(j) * G.pitch + x;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int off = PULL ? -(cy_of(k) * G.pitch + cx_of(k)) : 0;
+        f[k] = static_cast<R>(q[k * P + off]);
+    }
+}
+
+// ------------------------------------------------------------ collision
+
+// 1-D inverse transform: central moments (k0, k1, k2) about velocity v of a
+// 3-velocity set {0, +1, -1} -> populations (p0, p+, p-).
+template <typename R>
+__device__ __forceinline__ void inv1d(R k0, R k1, R k2, R v, R v2, R &p0, R &pp, R &pm) {
+    const R r1 = k1 + v * k0;
+    const R r2 = k2 + R(2) * v * k1 + v2 * k0;
+    p0 = k0 - r2;
+    pp = R(0.5) * (r2 + r1);
+    pm = R(0.5) * (r2 - r1);
+}
+
+// Post-collision values o[9] of one node from its pre-collision values p[9]
+// (f, or g = f - w rho0 in deviation mode) and the density gradient.
+//   COLL == kRC : Sec. 4 (central moments, equilibria Eq. 49, sources
+//                 (0, Fx, Fy, 0, ...), F / F^{-1} of App. B);
+//   COLL == kRNR: Sec. 3 (raw moments, Eq. 12 with the m_8 coefficient 1,
+//                 sources Eq. 13).
+// Both add the corrections of Eq. 23-27 with the strain rate of Eq. 37-38.
+// HU: omega_6 = omega_7 = omega_8 = 1 (the paper's setting), so the third-
+// and fourth-order pre-collision moments are not needed.
+template <typename R, bool DEV, int COLL, bool HU>
+__device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
+                                        const Consts<R> &K, R (&o)[9]) {
+    // x-sums of the three cy rows; (cx = 0, +1, -1) is (0,1,3), (2,5,6), (4,8,7)
+    const R s0z = p[0] + p[1] + p[3], s1z = p[1] - p[3], s2z = p[1] + p[3];
+    const R s0p = p[2] + p[5] + p[6], s1p = p[5] - p[6], s2p = p[5] + p[6];
+    const R s0m = p[4] + p[8] + p[7], s1m = p[8] - p[7], s2m = p[8] + p[7];
+    // raw moments r_mn = sum p cx^m cy^n (cy in units of a)
+    const R r02 = s0p + s0m;
+    const R r00 = s0z + r02;
+    const R r10 = s1z + s1p + s1m;
+    const R r20 = s2z + s2p + s2m;
+    const R r01 = s0p - s0m;
+    const R r11 = s1p - s1m;
+    // macroscopic fields, rho u = sum f e + F/2
+    const R rr = DEV ? K.rr : R(0);
+    const R rho = rr + r00;
+    const R irho = R(1) / rho;
+    const R ux = (r10 + K.hFx) * irho;
+    const R uy = (K.a * r01 + K.hFy) * irho;
+    const R ux2 = ux * ux, uy2 = uy * uy, uxuy = ux * uy;
+
+    // second-order non-equilibrium parts N3, N4, N5 (f level, paper basis)
+    // and the raw ones Q3, Q4 of Eq. 34-35 used by the strain rate
+    R N3, N4, N5, Q3, Q4;
+    R vy = R(0), vy2 = R(0), k20 = R(0), k10 = R(0);
+    if (COLL == kRC) {
+        vy = uy * K.inv_a;  // velocity in units of a
+        vy2 = vy * vy;
+        k20 = r20 - R(2) * ux * r10 + ux2 * r00;             // sum p (cx-ux)^2
+        const R k02 = r02 - R(2) * vy * r01 + vy2 * r00;     // sum p (cy-vy)^2
+        k10 = r10 - ux * r00;
+        const R k11 = (r11 - ux * r01) - vy * k10;           // sum p (cx-ux)(cy-vy)
+        const R ak02 = K.a2 * k02;
+        N3 = (k20 + ak02) - R(2) * K.s * r00 + rr * (ux2 + uy2);
+        N4 = (k20 - ak02) + rr * (ux2 - uy2);
+        N5 = K.a * k11 + rr * uxuy;
+        Q3 = N3 - (ux * K.Fx + uy * K.Fy);
+        Q4 = N4 - (ux * K.Fx - uy * K.Fy);
+    } else {
+        const R ar02 = K.a2 * r02;
+        N3 = (r20 + ar02) - R(2) * K.s * r00 - rho * (ux2 + uy2);
+        N4 = (r20 - ar02) - rho * (ux2 - uy2);
+        N5 = K.a * r11 - rho * uxuy;
+        Q3 = N3;
+        Q4 = N4;
+    }
+
+    // local strain rate (Eq. 37-38, coefficients Eq. 40 divided by rho) and
+    // the corrections (Eq. 23-26; Eq. 27: none on m_5)
+    R del3 = R(0), del4 = R(0);
+    if (corr) {
+        const R tx = K.e1 * ux * gx;  // B3 d_x rho = C3 d_x rho
+        const R ty = K.e2 * uy * gy;  // B4 d_y rho = -C4 d_y rho
+        const R M3 = Q3 - tx - ty;
+        const R M4 = Q4 - tx + ty;
+        const R b1 = K.b1c + R(1.5) * ux2, b2 = K.b2c + R(1.5) * uy2;
+        const R c1 = K.c1c + R(1.5) * ux2, c2 = K.c2c - R(1.5) * uy2;
+        const R idet = irho / (b1 * c2 - c1 * b2);
+        const R X = (c2 * M3 - b2 * M4) * idet;  // d ux / dx
+        const R Y = (b1 * M4 - c1 * M3) * idet;  // d uy / dy
+        const R t1 = K.q1 * (rho * X + ux * gx);
+        const R t2 = K.q2 * (rho * Y + uy * gy);
+        const R G3 = R(3) * rho * (ux2 * X + uy2 * Y);
+        const R G4 = R(3) * rho * (ux2 * X - uy2 * Y);
+        del3 = K.k3 * (t1 + t2 - G3);
+        del4 = K.k4 * (t1 - t2 - G4);
+    }
+
+    // post-collision moments in the paper basis, as deviations from rr * rest
+    R D0, D1, D2, D3, D4, D5, D6, D7, D8;
+    const R sux2 = K.s + ux2, suy2 = K.s + uy2;
+    if (COLL == kRC) {
+        D0 = r00;
+        D1 = K.hFx + rr * ux;  // relaxed first central moment = F/2 for any omega
+        D2 = K.hFy + rr * uy;
+        D3 = R(2) * K.s * r00 - rr * (ux2 + uy2) + K.om[3] * N3 + K.w[3] * del3;
+        D4 = -rr * (ux2 - uy2) + K.om[4] * N4 + K.w[4] * del4;
+        D5 = -rr * uxuy + K.om[5] * N5;
+        if (HU) {
+            D6 = rr * sux2 * uy;
+            D7 = rr * ux * suy2;
+            D8 = K.s2 * r00 - rr * (K.s * (ux2 + uy2) + ux2 * uy2);
+        } else {
+            const R r21 = s2p - s2m, r12 = s1p + s1m, r22 = s2p + s2m;
+            const R x21 = r21 - R(2) * ux * r11 + ux2 * r01;  // sum p (cx-ux)^2 cy
+            const R x11 = r11 - ux * r01;                     // sum p (cx-ux) cy
+            const R x12 = r12 - ux * r02;                     // sum p (cx-ux) cy^2
+            const R x22 = r22 - R(2) * ux * r12 + ux2 * r02;  // sum p (cx-ux)^2 cy^2
+            const R k21 = x21 - vy * k20;
+            const R k12 = x12 - R(2) * vy * x11 + vy2 * k10;
+            const R k22 = x22 - R(2) * vy * x21 + vy2 * k20;
+            const R M6 = K.a * k21 - rr * sux2 * uy;
+            const R M7 = K.a2 * k12 - rr * ux * suy2;
+            const R M8 = K.a2 * k22 + rr * sux2 * suy2;
+            D6 = K.om[6] * M6 + rr * sux2 * uy;
+            D7 = K.om[7] * M7 + rr * ux * suy2;
+            D8 = K.om[8] * M8 + K.w[8] * rho * K.s2 - rr * sux2 * suy2;
+        }
+    } else {
+        const R Fx = K.Fx, Fy = K.Fy;
+        const R phi3 = R(2) * (Fx * ux + Fy * uy);
+        const R phi4 = R(2) * (Fx * ux - Fy * uy);
+        const R phi5 = Fx * uy + Fy * ux;
+        const R phi6 = Fy * ux2 + R(2) * Fx * uxuy;
+        const R phi7 = Fx * uy2 + R(2) * Fy * uxuy;
+        const R phi8 = R(2) * (Fx * ux * uy2 + Fy * uy * ux2);
+        D0 = r00;
+        D1 = r10 + Fx;  // momentum gains F for any omega_1, omega_2
+        D2 = K.a * r01 + Fy;
+        D3 = R(2) * K.s * r00 + rho * (ux2 + uy2) + K.om[3] * N3 + K.w[3] * del3 + K.sw[3] * phi3;
+        D4 = rho * (ux2 - uy2) + K.om[4] * N4 + K.w[4] * del4 + K.sw[4] * phi4;
+        D5 = rho * uxuy + K.om[5] * N5 + K.sw[5] * phi5;
+        const R e6 = rho * uy * sux2, e7 = rho * ux * suy2;
+        const R e8x = r00 * K.s2 + rho * (K.s * (ux2 + uy2) + ux2 * uy2);  // eq8 - rr s^2
+        if (HU) {
+            D6 = e6 + R(0.5) * phi6;
+            D7 = e7 + R(0.5) * phi7;
+            D8 = e8x + R(0.5) * phi8;
+        } else {
+            const R r21 = s2p - s2m, r12 = s1p + s1m, r22 = s2p + s2m;
+            const R N6 = K.a * r21 - e6;
+            const R N7 = K.a2 * r12 - e7;
+            const R N8 = K.a2 * r22 - e8x;
+            D6 = e6 + K.om[6] * N6 + K.sw[6] * phi6;
+            D7 = e7 + K.om[7] * N7 + K.sw[7] * phi7;
+            D8 = e8x + K.om[8] * N8 + K.sw[8] * phi8;
+        }
+    }
+
+    // back to natural moments in (cx, cy) units
+    const R t20 = R(0.5) * (D3 + D4);
+    const R t02 = R(0.5) * (D3 - D4) * K.inv_a2;
+    const R t01 = D2 * K.inv_a, t11 = D5 * K.inv_a, t21 = D6 * K.inv_a;
+    const R t12 = D7 * K.inv_a2, t22 = D8 * K.inv_a2;
+    // RC: they are central moments about (ux, vy); RNR: raw (about 0)
+    const R sx = (COLL == kRC) ? ux : R(0), sx2 = (COLL == kRC) ? ux2 : R(0);
+    const R sy = (COLL == kRC) ? vy : R(0), sy2 = (COLL == kRC) ? vy2 : R(0);
+    // y stage for m = 0, 1, 2
+    R y00, y0p, y0m, y10, y1p, y1m, y20, y2p, y2m;
+    inv1d(D0, t01, t02, sy, sy2, y00, y0p, y0m);
+    inv1d(D1, t11, t12, sy, sy2, y10, y1p, y1m);
+    inv1d(t20, t21, t22, sy, sy2, y20, y2p, y2m);
+    // x stage for cy = 0, +1, -1
+    inv1d(y00, y10, y20, sx, sx2, o[0], o[1], o[3]);
+    inv1d(y0p, y1p, y2p, sx, sx2, o[2], o[5], o[6]);
+    inv1d(y0m, y1m, y2m, sx, sx2, o[4], o[8], o[7]);
+}
+
+// ------------------------------------------------------------ step kernel
+
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU>
+__global__ void __launch_bounds__(kBlock)
+step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, const Consts<R> K) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int b = blockIdx.x;
+    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous run of tiles so neighbouring segments share its L2
+    if (G.xcd_remap) b = (b & 7) * (G.nblocks >> 3) + (b >> 3);
+    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= G.ntile) return;
+    const int seg = tile % G.nseg;
+    const int chunk = tile / G.nseg;
+    const int x0 = seg * kWave;
+    const int j0 = chunk * G.rows;
+    const int j1 = min(j0 + G.rows, G.ny);
+    const int xlast = min(x0 + kWave - 1, G.nx - 1);
+    const int xraw = x0 + lane;
+    const bool active = xraw < G.nx;
+    const int x = min(xraw, G.nx - 1);
+    const ColInfo c = col_info(x, G);
+    const bool edge_cols = (x0 == 0) || (x0 + kWave >= G.nx);
+    const bool wall_left = (x0 == 0) && G.bc[kXmin] != kPeriodic;
+    const bool wall_right = (xlast == G.nx - 1) && G.bc[kXmax] != kPeriodic;
+
+    // halo pass: lane l gets rho at (x0 - 1, j0 + l) and (xlast + 1, j0 + l)
+    R hl = R(0), hr = R(0);
+    {
+        const RowInfo rh = row_info(min(j0 + lane, j1 - 1), G);
+        R f9[9];
+        if (!wall_left) {
+            load_node<S, R, PULL>(src, G, K, rh, col_info(x0 > 0 ? x0 - 1 : G.nx - 1, G), f9);
+            hl = sum9(f9);
+        }
+        if (!wall_right) {
+            load_node<S, R, PULL>(src, G, K, rh, col_info(xlast < G.nx - 1 ? xlast + 1 : 0, G), f9);
+            hr = sum9(f9);
+        }
+    }
+
+    auto load_row = [&](int jj, R (&f9)[9]) {
+        if (!edge_cols && jj > 0 && jj < G.ny - 1)
+            load_interior<S, R, PULL>(src, G, jj, x, f9);
+        else
+            load_node<S, R, PULL>(src, G, K, row_info(jj, G), c, f9);
+    };
+
+    // marching window: rho below (rb), populations and rho of the current row
+    R fc[9];
+    R rb;
+    const bool below = (j0 > 0) || G.bc[kYmin] == kPeriodic;
+    if (below) {
+        R f9[9];
+        load_row(j0 > 0 ? j0 - 1 : G.ny - 1, f9);
+        rb = sum9(f9);
+    }
+    load_row(j0, fc);
+    R rc = sum9(fc);
+    if (!below) rb = rc;  // wall: the missing neighbour's density is the node's own
+
+    for (int j = j0; j < j1; ++j) {
+        R fn[9];
+        R rn;
+        const bool above = (j + 1 < G.ny) || G.bc[kYmax] == kPeriodic;
+        if (above) {
+            load_row(j + 1 < G.ny ? j + 1 : 0, fn);
+            rn = sum9(fn);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) fn[k] = R(0);
+            rn = rc;
+        }
+        // left / right neighbour densities at the same time level
+        R rl = __shfl_up(rc, 1);
+        R rgt = __shfl_down(rc, 1);
+        const R hlj = readlane(hl, j - j0);
+        const R hrj = readlane(hr, j - j0);
+        if (lane == 0) rl = wall_left ? rc : hlj;
+        if (xraw == xlast) rgt = wall_right ? rc : hrj;
+        const R gx = (rgt - rl) * R(0.5);
+        const R gy = (rn - rb) * K.half_inv_a;
+
+        R out[9];
+        collide<R, DEV, COLL, HU>(fc, gx, gy, G.corr, K, out);
+        if (active) {
+            S *q = dst + static_cast<long long>(j) * G.pitch + xraw;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) q[k * G.plane] = static_cast<S>(out[k]);
+        }
+        rb = rc;
+        rc = rn;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fc[k] = fn[k];
+    }
+}
+
+template <typename S, typename R, bool DEV>
+static hipError_t step_dispatch(int coll, bool pull, bool hu, const void *src, void *dst,
+                                const Geometry &G, const Consts<R> &K, hipStream_t st) {
+    const dim3 grid(G.nblocks), block(kBlock);
+    const S *s = static_cast<const S *>(src);
+    S *d = static_cast<S *>(dst);
+#define LBM_STEP(C, P, H) \
+    hipLaunchKernelGGL((step_kernel<S, R, DEV, C, P, H>), grid, block, 0, st, s, d, G, K)
+    if (coll == kRC) {
+        if (pull) {
+            if (hu) LBM_STEP(kRC, true, true); else LBM_STEP(kRC, true, false);
+        } else {
+            if (hu) LBM_STEP(kRC, false, true); else LBM_STEP(kRC, false, false);
+        }
+    } else {
+        if (pull) {
+            if (hu) LBM_STEP(kRNR, true, true); else LBM_STEP(kRNR, true, false);
+        } else {
+            if (hu) LBM_STEP(kRNR, false, true); else LBM_STEP(kRNR, false, false);
+        }
+    }
+#undef LBM_STEP
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int prec, int coll, bool pull, bool hu, const void *src, void *dst,
+                       const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
+                       hipStream_t st) {
+    switch (prec) {
+    case kFP64: return step_dispatch<double, double, false>(coll, pull, hu, src, dst, G, Kd, st);
+    case kFP32Dev: return step_dispatch<float, float, true>(coll, pull, hu, src, dst, G, Kf, st);
+    case kFP64Dev: return step_dispatch<double, double, true>(coll, pull, hu, src, dst, G, Kd, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------ conversions
+
+// Equilibrium in product form: feq_k = rho Px(cx_k) Py(cy_k) with
+// Px(0) = 1 - s - ux^2, Px(+-1) = (s + ux^2 +- ux)/2,
+// Py(0) = 1 - (s + uy^2)/a^2, Py(+-1) = (s + uy^2 +- a uy)/(2 a^2);
+// this is T^{-1} F(-u) applied to Eq. 49 without corrections.
+__device__ __forceinline__ double px_of(int cx, double s, double u) {
+    return cx == 0 ? 1.0 - s - u * u : 0.5 * (s + u * u + cx * u);
+}
+__device__ __forceinline__ double py_of(int cy, double s, double a, double u) {
+    const double ia2 = 1.0 / (a * a);
+    return cy == 0 ? 1.0 - (s + u * u) * ia2 : 0.5 * (s + u * u + cy * a * u) * ia2;
+}
+
+template <typename S>
+__global__ void init_feq_kernel(S *__restrict__ dst, const double *__restrict__ rho,
+                                const double *__restrict__ ux, const double *__restrict__ uy,
+                                const Geometry G, const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        const double r = rho ? rho[idx] : H.rho0;
+        const double vx = ux ? ux[idx] : 0.0, vy = uy ? uy[idx] : 0.0;
+        const long long o = static_cast<long long>(j) * G.pitch + x;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double f = r * px_of(cx_of(k), H.s, vx) * py_of(cy_of(k), H.s, H.a, vy);
+            if (H.dev) f -= H.rho0 * H.wrest[k];
+            dst[k * G.plane + o] = static_cast<S>(f);
+        }
+    }
+}
+
+template <typename S>
+__global__ void set_pop_kernel(S *__restrict__ dst, const double *__restrict__ f,
+                               const Geometry G, const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        const long long o = static_cast<long long>(j) * G.pitch + x;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double v = f[k * n + idx];
+            if (H.dev) v -= H.rho0 * H.wrest[k];
+            dst[k * G.plane + o] = static_cast<S>(v);
+        }
+    }
+}
+
+template <typename S, bool PULL>
+__global__ void get_pop_kernel(const S *__restrict__ src, double *__restrict__ f,
+                               const Geometry G, const Consts<double> K, const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        double f9[9];
+        load_node<S, double, PULL>(src, G, K, row_info(j, G), col_info(x, G), f9);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k * n + idx] = f9[k] + (H.dev ? H.rho0 * H.wrest[k] : 0.0);
+    }
+}
+
+// rho, u of one node from its pre-collision values, in FP64
+__device__ __forceinline__ void macro_of(const double (&f9)[9], const HostSide &H, double &r,
+                                         double &vx, double &vy) {
+    double s = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        s += f9[k];
+        jx += cx_of(k) * f9[k];
+        jy += cy_of(k) * f9[k];
+    }
+    r = s + (H.dev ? H.rho0 : 0.0);
+    vx = (jx + 0.5 * H.Fx) / r;
+    vy = (H.a * jy + 0.5 * H.Fy) / r;
+}
+
+template <typename S, bool PULL>
+__global__ void moments_kernel(const S *__restrict__ src, double *__restrict__ rho,
+                               double *__restrict__ ux, double *__restrict__ uy,
+                               const Geometry G, const Consts<double> K, const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        double f9[9], r, vx, vy;
+        load_node<S, double, PULL>(src, G, K, row_info(j, G), col_info(x, G), f9);
+        macro_of(f9, H, r, vx, vy);
+        rho[idx] = r;
+        ux[idx] = vx;
+        uy[idx] = vy;
+    }
+}
+
+// ------------------------------------------------------------ reductions
+
+// Deterministic FP64 block sum of 4 values: wavefront shuffle tree, then
+// the wavefront totals in a fixed order.
+__device__ __forceinline__ void block_sum4(double (&v)[4], double *out) {
+    __shared__ double part[kReduceBlock / kWave][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int off = kWave / 2; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) part[w][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 4; ++q) {
+            double t = 0.0;
+            for (int i = 0; i < kReduceBlock / kWave; ++i) t += part[i][q];
+            out[q] = t;
+        }
+    }
+}
+
+template <typename S, bool PULL>
+__global__ void __launch_bounds__(kReduceBlock)
+sums_kernel(const S *__restrict__ src, double *__restrict__ partials, const Geometry G,
+            const Consts<double> K, const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        double f9[9], r, vx, vy;
+        load_node<S, double, PULL>(src, G, K, row_info(j, G), col_info(x, G), f9);
+        macro_of(f9, H, r, vx, vy);
+        acc[0] += r;
+        acc[1] += r * vx;
+        acc[2] += r * vy;
+        if (!isfinite(r) || !isfinite(vx) || !isfinite(vy)) acc[3] = 1.0;
+    }
+    block_sum4(acc, partials + 4 * blockIdx.x);
+}
+
+template <typename SC, typename SP, bool PC, bool PP>
+__global__ void __launch_bounds__(kReduceBlock)
+residual_kernel(const SC *__restrict__ cur, const SP *__restrict__ prev,
+                double *__restrict__ partials, const Geometry G, const Consts<double> K,
+                const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        const RowInfo ri = row_info(j, G);
+        const ColInfo ci = col_info(x, G);
+        double f9[9], r, vx, vy, r0, wx, wy;
+        load_node<SC, double, PC>(cur, G, K, ri, ci, f9);
+        macro_of(f9, H, r, vx, vy);
+        load_node<SP, double, PP>(prev, G, K, ri, ci, f9);
+        macro_of(f9, H, r0, wx, wy);
+        const double dx = vx - wx, dy = vy - wy;
+        acc[0] += dx * dx + dy * dy;
+        acc[1] += vx * vx + vy * vy;
+        if (!isfinite(vx) || !isfinite(vy) || !isfinite(wx) || !isfinite(wy)) acc[3] = 1.0;
+    }
+    block_sum4(acc, partials + 4 * blockIdx.x);
+}
+
+// sums the per-block partials in a fixed order; NaN flags are or-ed (max)
+__global__ void __launch_bounds__(kReduceBlock)
+finalize_kernel(const double *__restrict__ partials, int nparts, double *__restrict__ out) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        acc[0] += partials[4 * i + 0];
+        acc[1] += partials[4 * i + 1];
+        acc[2] += partials[4 * i + 2];
+        acc[3] = fmax(acc[3], partials[4 * i + 3]);
+    }
+    // flag: any non-zero survives the sum as non-zero
+    block_sum4(acc, out);
+}
+
+static int reduce_blocks(const Geometry &G) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    long long b = (n + kReduceBlock - 1) / kReduceBlock;
+    if (b > kMaxPartials) b = kMaxPartials;
+    return static_cast<int>(b);
+}
+
+static int conv_blocks(const Geometry &G) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    long long b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    return static_cast<int>(b);
+}
+
+hipError_t launch_init_feq(int prec, void *dst, const double *rho, const double *ux,
+                           const double *uy, const Geometry &G, const HostSide &H,
+                           hipStream_t st) {
+    if (prec == kFP32Dev)
+        hipLaunchKernelGGL(init_feq_kernel<float>, dim3(conv_blocks(G)), dim3(256), 0, st,
+                           static_cast<float *>(dst), rho, ux, uy, G, H);
+    else
+        hipLaunchKernelGGL(init_feq_kernel<double>, dim3(conv_blocks(G)), dim3(256), 0, st,
+                           static_cast<double *>(dst), rho, ux, uy, G, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_populations(int prec, void *dst, const double *f, const Geometry &G,
+                                  const HostSide &H, hipStream_t st) {
+    if (prec == kFP32Dev)
+        hipLaunchKernelGGL(set_pop_kernel<float>, dim3(conv_blocks(G)), dim3(256), 0, st,
+                           static_cast<float *>(dst), f, G, H);
+    else
+        hipLaunchKernelGGL(set_pop_kernel<double>, dim3(conv_blocks(G)), dim3(256), 0, st,
+                           static_cast<double *>(dst), f, G, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_populations(int prec, bool pull, const void *src, double *f,
+                                  const Geometry &G, const Consts<double> &Kd,
+                                  const Consts<float> &, const HostSide &H, hipStream_t st) {
+    const dim3 grid(conv_blocks(G)), block(256);
+    if (prec == kFP32Dev) {
+        const float *s = static_cast<const float *>(src);
+        if (pull) hipLaunchKernelGGL((get_pop_kernel<float, true>), grid, block, 0, st, s, f, G, Kd, H);
+        else hipLaunchKernelGGL((get_pop_kernel<float, false>), grid, block, 0, st, s, f, G, Kd, H);
+    } else {
+        const double *s = static_cast<const double *>(src);
+        if (pull) hipLaunchKernelGGL((get_pop_kernel<double, true>), grid, block, 0, st, s, f, G, Kd, H);
+        else hipLaunchKernelGGL((get_pop_kernel<double, false>), grid, block, 0, st, s, f, G, Kd, H);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int prec, bool pull, const void *src, double *rho, double *ux,
+                          double *uy, const Geometry &G, const Consts<double> &Kd,
+                          const Consts<float> &, const HostSide &H, hipStream_t st) {
+    const dim3 grid(conv_blocks(G)), block(256);
+    if (prec == kFP32Dev) {
+        const float *s = static_cast<const float *>(src);
+        if (pull) hipLaunchKernelGGL((moments_kernel<float, true>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
+        else hipLaunchKernelGGL((moments_kernel<float, false>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
+    } else {
+        const double *s = static_cast<const double *>(src);
+        if (pull) hipLaunchKernelGGL((moments_kernel<double, true>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
+        else hipLaunchKernelGGL((moments_kernel<double, false>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, double *out,
+                       const Geometry &G, const Consts<double> &Kd, const Consts<float> &,
+                       const HostSide &H, hipStream_t st) {
+    const int nb = reduce_blocks(G);
+    const dim3 grid(nb), block(kReduceBlock);
+    if (prec == kFP32Dev) {
+        const float *s = static_cast<const float *>(src);
+        if (pull) hipLaunchKernelGGL((sums_kernel<float, true>), grid, block, 0, st, s, partials, G, Kd, H);
+        else hipLaunchKernelGGL((sums_kernel<float, false>), grid, block, 0, st, s, partials, G, Kd, H);
+    } else {
+        const double *s = static_cast<const double *>(src);
+        if (pull) hipLaunchKernelGGL((sums_kernel<double, true>), grid, block, 0, st, s, partials, G, Kd, H);
+        else hipLaunchKernelGGL((sums_kernel<double, false>), grid, block, 0, st, s, partials, G, Kd, H);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
+template <typename S>
+static void residual_dispatch(bool pc, const S *cur, bool pp, const S *prev, double *partials,
+                              const Geometry &G, const Consts<double> &Kd, const HostSide &H,
+                              int nb, hipStream_t st) {
+    const dim3 grid(nb), block(kReduceBlock);
+    if (pc && pp) hipLaunchKernelGGL((residual_kernel<S, S, true, true>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+    else if (pc) hipLaunchKernelGGL((residual_kernel<S, S, true, false>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+    else if (pp) hipLaunchKernelGGL((residual_kernel<S, S, false, true>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+    else hipLaunchKernelGGL((residual_kernel<S, S, false, false>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+}
+
+hipError_t launch_residual(int prec, bool pull_cur, const void *cur, bool pull_prev,
+                           const void *prev, double *partials, double *out, const Geometry &G,
+                           const Consts<double> &Kd, const Consts<float> &, const HostSide &H,
+                           hipStream_t st) {
+    const int nb = reduce_blocks(G);
+    if (prec == kFP32Dev)
+        residual_dispatch<float>(pull_cur, static_cast<const float *>(cur), pull_prev,
+                                 static_cast<const float *>(prev), partials, G, Kd, H, nb, st);
+    else
+        residual_dispatch<double>(pull_cur, static_cast<const double *>(cur), pull_prev,
+                                  static_cast<const double *>(prev), partials, G, Kd, H, nb, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

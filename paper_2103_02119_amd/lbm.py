@@ -1,0 +1,283 @@
+"""Python binding of the C ABI in include/lbm.h (liblbm.so).
+
+Argument marshalling only: every function here forwards to the HIP library
+with the same name and turns a negative status into LbmError.  There is no
+CPU fallback -- if liblbm.so is missing or no GPU is usable, calls raise.
+PyTorch is used (optionally) only to own the device population buffers and
+to supply the HIP stream the library enqueues on.
+
+Host arrays are numpy float64, C order: scalar fields (ny, nx), populations
+(9, ny, nx).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
+LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_MOVING_WALL = 0, 1, 2
+LBM_FACE_XMIN, LBM_FACE_XMAX, LBM_FACE_YMIN, LBM_FACE_YMAX = 0, 1, 2, 3
+LBM_RC, LBM_RNR = 0, 1
+LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV = 0, 1, 2
+
+EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
+           "lbm_moments", "lbm_residual", "lbm_sums", "lbm_get_populations",
+           "lbm_set_populations", "lbm_steps_done", "lbm_launch_shape", "lbm_last_error",
+           "lbm_destroy")
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class lbm_bc(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int * 4), ("u_wall", (ctypes.c_double * 2) * 4)]
+
+
+class lbm_opts(ctypes.Structure):
+    _fields_ = [
+        ("cs2", ctypes.c_double),
+        ("force", ctypes.c_double * 2),
+        ("rho0", ctypes.c_double),
+        ("collision", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("corrections", ctypes.c_int),
+        ("rows_per_wave", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("f_a", ctypes.c_void_p),
+        ("f_b", ctypes.c_void_p),
+        ("f_bytes", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_CTX = ctypes.c_void_p
+
+
+def load():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    L.lbm_default_opts.argtypes = [ctypes.POINTER(lbm_opts)]
+    L.lbm_default_opts.restype = None
+    L.lbm_required_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+    L.lbm_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D,
+                             ctypes.POINTER(lbm_bc), ctypes.POINTER(lbm_opts),
+                             ctypes.POINTER(_CTX)]
+    L.lbm_set_fields.argtypes = [_CTX, _D, _D, _D]
+    L.lbm_step.argtypes = [_CTX, ctypes.c_long]
+    L.lbm_moments.argtypes = [_CTX, _D, _D, _D]
+    L.lbm_residual.argtypes = [_CTX, _D]
+    L.lbm_sums.argtypes = [_CTX, _D]
+    L.lbm_get_populations.argtypes = [_CTX, _D]
+    L.lbm_set_populations.argtypes = [_CTX, _D]
+    L.lbm_steps_done.argtypes = [_CTX]
+    L.lbm_steps_done.restype = ctypes.c_long
+    L.lbm_launch_shape.argtypes = [_CTX, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int)]
+    L.lbm_last_error.argtypes = [_CTX]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_destroy.argtypes = [_CTX]
+    for name in ("lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step", "lbm_moments",
+                 "lbm_residual", "lbm_sums", "lbm_get_populations", "lbm_set_populations",
+                 "lbm_launch_shape", "lbm_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, ctx=None):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error(ctx).decode(errors="replace")
+        raise LbmError(rc, msg)
+
+
+def _in(arr, shape):
+    if arr is None:
+        return None, None
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a, a.ctypes.data_as(_D)
+
+
+# ----------------------------------------------------------- same-name calls
+
+def lbm_default_opts() -> lbm_opts:
+    o = lbm_opts()
+    load().lbm_default_opts(ctypes.byref(o))
+    return o
+
+
+def lbm_required_bytes(nx: int, ny: int, precision: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().lbm_required_bytes(nx, ny, precision, ctypes.byref(n)))
+    return n.value
+
+
+def make_bc(types=(LBM_BC_PERIODIC,) * 4, u_wall=((0.0, 0.0),) * 4) -> lbm_bc:
+    b = lbm_bc()
+    for f in range(4):
+        b.type[f] = int(types[f])
+        b.u_wall[f][0] = float(u_wall[f][0])
+        b.u_wall[f][1] = float(u_wall[f][1])
+    return b
+
+
+def lbm_create(nx: int, ny: int, r: float, rates, bc: lbm_bc, opts: lbm_opts | None = None):
+    rates_arr = (ctypes.c_double * 9)(*[float(w) for w in rates])
+    ctx = _CTX()
+    rc = load().lbm_create(int(nx), int(ny), float(r), rates_arr, ctypes.byref(bc),
+                           ctypes.byref(opts) if opts is not None else None, ctypes.byref(ctx))
+    _check(rc, None)
+    return ctx
+
+
+def lbm_set_fields(ctx, nx, ny, rho=None, ux=None, uy=None):
+    keep = [_in(v, (ny, nx)) for v in (rho, ux, uy)]
+    _check(load().lbm_set_fields(ctx, *[k[1] for k in keep]), ctx)
+
+
+def lbm_step(ctx, n: int):
+    _check(load().lbm_step(ctx, int(n)), ctx)
+
+
+def lbm_moments(ctx, nx, ny):
+    rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
+    _check(load().lbm_moments(ctx, rho.ctypes.data_as(_D), ux.ctypes.data_as(_D),
+                              uy.ctypes.data_as(_D)), ctx)
+    return rho, ux, uy
+
+
+def lbm_residual(ctx) -> float:
+    R = ctypes.c_double()
+    _check(load().lbm_residual(ctx, ctypes.byref(R)), ctx)
+    return R.value
+
+
+def lbm_sums(ctx):
+    out = np.zeros(3)
+    _check(load().lbm_sums(ctx, out.ctypes.data_as(_D)), ctx)
+    return out
+
+
+def lbm_get_populations(ctx, nx, ny):
+    f = np.empty((9, ny, nx))
+    _check(load().lbm_get_populations(ctx, f.ctypes.data_as(_D)), ctx)
+    return f
+
+
+def lbm_set_populations(ctx, nx, ny, f):
+    a, p = _in(f, (9, ny, nx))
+    _check(load().lbm_set_populations(ctx, p), ctx)
+
+
+def lbm_steps_done(ctx) -> int:
+    return load().lbm_steps_done(ctx)
+
+
+def lbm_launch_shape(ctx):
+    r, w = ctypes.c_int(), ctypes.c_int()
+    _check(load().lbm_launch_shape(ctx, ctypes.byref(r), ctypes.byref(w)), ctx)
+    return r.value, w.value
+
+
+def lbm_last_error(ctx=None) -> str:
+    return load().lbm_last_error(ctx).decode(errors="replace")
+
+
+def lbm_destroy(ctx):
+    if ctx:
+        load().lbm_destroy(ctx)
+
+
+# ----------------------------------------------------------- convenience
+
+class Lattice:
+    """Owns one lbm_ctx.  With torch_buffers=True the two population buffers
+    are torch CUDA tensors and the library runs on torch's current stream."""
+
+    def __init__(self, nx, ny, r, rates, bc_types=(LBM_BC_PERIODIC,) * 4,
+                 u_wall=((0.0, 0.0),) * 4, cs2=0.0, force=(0.0, 0.0), rho0=1.0,
+                 collision=LBM_RC, precision=LBM_FP64, corrections=True, rows_per_wave=0,
+                 torch_buffers=True):
+        self.nx, self.ny, self.r = int(nx), int(ny), float(r)
+        o = lbm_default_opts()
+        o.cs2 = float(cs2)
+        o.force[0], o.force[1] = float(force[0]), float(force[1])
+        o.rho0 = float(rho0)
+        o.collision = int(collision)
+        o.precision = int(precision)
+        o.corrections = 1 if corrections else 0
+        o.rows_per_wave = int(rows_per_wave)
+        self._buffers = None
+        if torch_buffers:
+            import torch
+            nbytes = lbm_required_bytes(self.nx, self.ny, int(precision))
+            self._buffers = [torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+                             for _ in range(2)]
+            o.f_a = self._buffers[0].data_ptr()
+            o.f_b = self._buffers[1].data_ptr()
+            o.f_bytes = nbytes
+            o.stream = torch.cuda.current_stream().cuda_stream
+        self.opts = o
+        self.ctx = lbm_create(self.nx, self.ny, self.r, rates, make_bc(bc_types, u_wall), o)
+
+    def set_fields(self, rho=None, ux=None, uy=None):
+        lbm_set_fields(self.ctx, self.nx, self.ny, rho, ux, uy)
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+
+    def moments(self):
+        return lbm_moments(self.ctx, self.nx, self.ny)
+
+    def residual(self):
+        return lbm_residual(self.ctx)
+
+    def sums(self):
+        return lbm_sums(self.ctx)
+
+    def get_populations(self):
+        return lbm_get_populations(self.ctx, self.nx, self.ny)
+
+    def set_populations(self, f):
+        lbm_set_populations(self.ctx, self.nx, self.ny, f)
+
+    def launch_shape(self):
+        return lbm_launch_shape(self.ctx)
+
+    @property
+    def steps_done(self):
+        return lbm_steps_done(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,113 @@
+"""The C ABI library loads and exports every entry point include/lbm.h
+declares; host-side argument validation works without a GPU (no compute
+call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2103_02119_amd import lbm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("lbm_create", "lbm_step", "lbm_moments", "lbm_residual", "lbm_sums",
+                     "lbm_set_fields", "lbm_get_populations", "lbm_set_populations",
+                     "lbm_destroy", "lbm_last_error", "lbm_required_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_uses_the_same_names():
+    assert sorted(L.EXPORTS) == _declared_functions()
+    for name in L.EXPORTS:
+        assert callable(getattr(L, name))
+
+
+def test_required_bytes():
+    assert L.lbm_required_bytes(512, 1024, L.LBM_FP32_DEV) == 9 * 512 * 1024 * 4
+    assert L.lbm_required_bytes(100, 10, L.LBM_FP64) == 9 * 128 * 10 * 8
+    assert L.lbm_required_bytes(3, 3, L.LBM_FP64_DEV) == 9 * 64 * 3 * 8
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_required_bytes(2, 10, L.LBM_FP64)
+    assert e.value.code == L.LBM_E_INVAL
+    with pytest.raises(L.LbmError):
+        L.lbm_required_bytes(10, 10, 7)
+    with pytest.raises(L.LbmError):
+        L.lbm_required_bytes(1 << 16, 1 << 16, L.LBM_FP64)
+
+
+def _bc(types=(0, 0, 1, 1)):
+    return L.make_bc(types)
+
+
+@pytest.mark.parametrize("kwargs,fragment", [
+    (dict(nx=2), "nx and ny"),
+    (dict(r=0.0), "r must be"),
+    (dict(r=-1.0), "r must be"),
+    (dict(rates=[1.0] * 8 + [2.0]), "rates[8]"),
+    (dict(rates=[0.0] + [1.0] * 8), "rates[0]"),
+    (dict(cs2=0.25), "cs2"),
+    (dict(cs2=-0.1), "cs2"),
+    (dict(bc=(0, 1, 1, 1)), "opposite faces"),
+    (dict(bc=(0, 0, 1, 5)), "unknown boundary"),
+    (dict(collision=3), "unknown collision"),
+    (dict(precision=9), "unknown precision"),
+    (dict(rows_per_wave=65), "rows_per_wave"),
+])
+def test_invalid_arguments_are_rejected_before_touching_the_device(kwargs, fragment):
+    args = dict(nx=32, ny=16, r=0.5, rates=[1.0] * 9, bc=(0, 0, 1, 1), cs2=0.16, collision=0,
+                precision=0, rows_per_wave=0)
+    args.update(kwargs)
+    o = L.lbm_default_opts()
+    o.cs2 = args["cs2"]
+    o.collision = args["collision"]
+    o.precision = args["precision"]
+    o.rows_per_wave = args["rows_per_wave"]
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_create(args["nx"], args["ny"], args["r"], args["rates"], _bc(args["bc"]), o)
+    assert e.value.code == L.LBM_E_INVAL
+    assert fragment in str(e.value)
+    assert fragment in L.lbm_last_error(None)
+
+
+def test_caller_buffers_must_be_paired_and_large_enough():
+    o = L.lbm_default_opts()
+    o.f_a = 0x1000
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_create(32, 16, 0.5, [1.0] * 9, _bc(), o)
+    assert e.value.code == L.LBM_E_INVAL
+    o.f_b = 0x2000
+    o.f_bytes = 16
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_create(32, 16, 0.5, [1.0] * 9, _bc(), o)
+    assert e.value.code == L.LBM_E_INVAL
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU driver is present")
+def test_no_gpu_fails_loudly():
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_create(32, 16, 0.5, [1.0] * 9, _bc())
+    assert e.value.code == L.LBM_E_DEVICE
+
+
+def test_default_opts():
+    o = L.lbm_default_opts()
+    assert o.rho0 == 1.0 and o.collision == L.LBM_RC and o.precision == L.LBM_FP64
+    assert o.corrections == 1 and o.cs2 == 0.0 and o.stream is None

@@ -1,0 +1,374 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars (per field, max-norm relative to the oracle's max |value|):
+  FP64 and FP64-deviation storage: 1e-12;
+  FP32-deviation storage: 1e-5 on velocity.
+Inputs are seeded random near-equilibrium states (paper_2103_02119_amd.inputs)
+on grids that span several 64-column segments with a ragged tail, plus the
+degenerate shapes (3 x 3, one-column tails, one-row chunks)."""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+
+import oracle as O
+from paper_2103_02119_amd import inputs as I
+from paper_2103_02119_amd import lbm as L
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_U = 1e-5
+
+CASES = {
+    # name: (a, cs2, bc types, wall velocities, force)
+    "periodic": (0.5, 0.16, (0, 0, 0, 0), ((0, 0),) * 4, (1e-5, -2e-5)),
+    "channel": (0.25, 0.04, (0, 0, 1, 1), ((0, 0),) * 4, (2e-6, 0.0)),
+    "cavity": (0.5, 0.16, (1, 1, 1, 2), ((0, 0), (0, 0), (0, 0), (0.05, 0.0)), (0.0, 0.0)),
+    "xwalls": (2.0, 0.3, (1, 1, 0, 0), ((0, 0),) * 4, (0.0, 1e-5)),
+    "xmoving": (1.0, 1 / 3, (2, 2, 0, 0), ((0, 0.03), (0, -0.02), (0, 0), (0, 0)), (0.0, 0.0)),
+    "box_all_moving": (0.5, 0.16, (2, 2, 2, 2),
+                       ((0.0, 0.01), (0.0, -0.01), (-0.02, 0.0), (0.03, 0.0)), (0.0, 0.0)),
+}
+RATES_HU = [1.0, 1.0, 1.0, 1.1, 1.3, 1.3, 1.0, 1.0, 1.0]
+RATES_GEN = [1.0, 0.7, 1.2, 1.1, 1.3, 1.3, 0.9, 1.2, 1.4]
+
+
+def rel(x, ref):
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def make(name, nx, ny, coll=0, prec=0, rates=RATES_HU, corr=True, rows=0, torch_buffers=True):
+    a, cs2, bc, uw, F = CASES[name]
+    p = O.make_params(nx, ny, a, cs2, rates, force=F, collision=coll, corrections=corr, bc=bc,
+                      u_wall=uw)
+    lat = L.Lattice(nx, ny, a, rates, bc_types=bc, u_wall=uw, cs2=cs2, force=F,
+                    collision=coll, precision=prec, corrections=corr, rows_per_wave=rows,
+                    torch_buffers=torch_buffers)
+    return p, lat
+
+
+def random_state(p, seed=2103, noise=1e-3):
+    rho, ux, uy = I.random_fields(seed, p.nx, p.ny)
+    return O.init(p, rho, ux, uy) * I.relative_noise(seed, p.nx, p.ny, noise)
+
+
+def announce(*args):
+    print("case:", *args, flush=True)
+
+
+# ---------------------------------------------------------------- FP64
+
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP64_DEV])
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_random_state_steps(name, coll, prec):
+    nx, ny = 150, 70  # 3 segments (64 + 64 + 22), several row chunks
+    announce(name, coll, prec, nx, ny)
+    p, lat = make(name, nx, ny, coll, prec)
+    f0 = random_state(p)
+    lat.set_populations(f0)
+    ref = f0
+    done = 0
+    for n in (1, 1, 3):  # the first step reads in place, later ones pull
+        lat.step(n)
+        ref = O.run(p, ref, n)
+        done += n
+        got = lat.get_populations()
+        assert rel(got, ref) < TOL64, (name, done)
+    r_o, ux_o, uy_o = O.moments(p, ref)
+    r_g, ux_g, uy_g = lat.moments()
+    assert rel(r_g, r_o) < TOL64
+    assert rel(ux_g, ux_o) < TOL64
+    assert rel(uy_g, uy_o) < TOL64
+    lat.close()
+
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+@pytest.mark.parametrize("name", ["periodic", "cavity", "xmoving"])
+def test_fp64_general_rates_and_no_corrections(name, coll):
+    nx, ny = 97, 45
+    for rates, corr in ((RATES_GEN, True), (RATES_HU, False), (RATES_GEN, False)):
+        announce(name, coll, rates, corr)
+        p, lat = make(name, nx, ny, coll, L.LBM_FP64, rates=rates, corr=corr)
+        f0 = random_state(p, seed=7)
+        lat.set_populations(f0)
+        lat.step(4)
+        assert rel(lat.get_populations(), O.run(p, f0, 4)) < TOL64
+        lat.close()
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (4, 3), (3, 5), (64, 4), (65, 6), (128, 3), (130, 9)])
+@pytest.mark.parametrize("name", ["periodic", "cavity", "xwalls"])
+def test_degenerate_shapes(name, shape):
+    nx, ny = shape
+    announce(name, shape)
+    p, lat = make(name, nx, ny, 0, L.LBM_FP64)
+    f0 = random_state(p, seed=11)
+    lat.set_populations(f0)
+    lat.step(3)
+    assert rel(lat.get_populations(), O.run(p, f0, 3)) < TOL64
+    lat.close()
+
+
+@pytest.mark.parametrize("name", ["periodic", "cavity"])
+def test_results_do_not_depend_on_the_launch_shape(name):
+    nx, ny = 150, 70
+    p, _ = make(name, nx, ny)
+    f0 = random_state(p, seed=3)
+    outs = []
+    for rows in (1, 2, 3, 7, 32, 64):
+        announce(name, "rows", rows)
+        _, lat = make(name, nx, ny, rows=rows)
+        assert lat.launch_shape()[0] == min(rows, ny)
+        lat.set_populations(f0)
+        lat.step(3)
+        outs.append(lat.get_populations())
+        lat.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_library_allocated_buffers_and_default_stream():
+    p, lat = make("cavity", 80, 40, torch_buffers=False)
+    f0 = random_state(p, seed=5)
+    lat.set_populations(f0)
+    lat.step(2)
+    assert rel(lat.get_populations(), O.run(p, f0, 2)) < TOL64
+    lat.close()
+
+
+def test_set_fields_matches_oracle_init():
+    for name in ("periodic", "cavity"):
+        for prec in (L.LBM_FP64, L.LBM_FP64_DEV):
+            p, lat = make(name, 70, 33, prec=prec)
+            rho, ux, uy = I.random_fields(9, 70, 33)
+            lat.set_fields(rho, ux, uy)
+            assert rel(lat.get_populations(), O.init(p, rho, ux, uy)) < 1e-14
+            r, vx, vy = lat.moments()
+            assert rel(r, rho) < 1e-14
+            lat.close()
+
+
+def test_populations_roundtrip():
+    p, lat = make("periodic", 100, 20)
+    f0 = random_state(p, seed=12)
+    lat.set_populations(f0)
+    assert np.array_equal(lat.get_populations(), f0)
+    lat.close()
+
+
+# ---------------------------------------------------------------- reductions
+
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+@pytest.mark.parametrize("name", ["periodic", "cavity", "channel"])
+def test_sums_and_residual(name, prec):
+    nx, ny = 150, 70
+    p, lat = make(name, nx, ny, prec=prec)
+    f0 = random_state(p, seed=21)
+    lat.set_populations(f0)
+    with pytest.raises(L.LbmError) as e:
+        lat.residual()
+    assert e.value.code == L.LBM_E_STATE
+    lat.step(5)
+    f4 = O.run(p, f0, 4)
+    f5 = O.run(p, f4, 1)
+    r4, ux4, uy4 = O.moments(p, f4)
+    r5, ux5, uy5 = O.moments(p, f5)
+    sums = lat.sums()
+    expect = np.array([r5.sum(), (r5 * ux5).sum(), (r5 * uy5).sum()])
+    R_ref = np.sqrt(((ux5 - ux4) ** 2 + (uy5 - uy4) ** 2).sum() / (ux5 ** 2 + uy5 ** 2).sum())
+    R = lat.residual()
+    if prec == L.LBM_FP64:
+        assert abs(sums[0] - expect[0]) / expect[0] < 1e-13
+        assert abs(sums[1] - expect[1]) < 1e-12 * np.abs(r5 * ux5).sum()
+        assert abs(sums[2] - expect[2]) < 1e-12 * np.abs(r5 * uy5).sum()
+        assert R == pytest.approx(R_ref, rel=1e-10)
+    else:
+        assert abs(sums[0] - expect[0]) / expect[0] < 1e-7
+        assert R == pytest.approx(R_ref, rel=1e-3)
+    lat.close()
+
+
+def test_first_step_residual_and_unstable_flag():
+    """The residual of the very first step compares the pulled state with the
+    in-place state that set_populations wrote."""
+    p, lat = make("cavity", 64, 16)
+    f0 = random_state(p, seed=22)
+    lat.set_populations(f0)
+    lat.step(1)
+    f1 = O.run(p, f0, 1)
+    _, ux0, uy0 = O.moments(p, f0)
+    _, ux1, uy1 = O.moments(p, f1)
+    R_ref = np.sqrt(((ux1 - ux0) ** 2 + (uy1 - uy0) ** 2).sum() / (ux1 ** 2 + uy1 ** 2).sum())
+    assert lat.residual() == pytest.approx(R_ref, rel=1e-10)
+    f = lat.get_populations()
+    f[3, 5, 7] = np.nan
+    lat.set_populations(f)
+    with pytest.raises(L.LbmError) as e:
+        lat.sums()
+    assert e.value.code == L.LBM_E_UNSTABLE
+    lat.step(1)
+    with pytest.raises(L.LbmError) as e:
+        lat.residual()
+    assert e.value.code == L.LBM_E_UNSTABLE
+    lat.close()
+
+
+# ---------------------------------------------------------------- FP32
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_deviation_velocity(name, coll):
+    nx, ny = 150, 70
+    announce("fp32", name, coll)
+    p, lat = make(name, nx, ny, coll, L.LBM_FP32_DEV)
+    f0 = random_state(p, seed=31)
+    lat.set_populations(f0)
+    lat.step(50)
+    ref = O.run(p, f0, 50)
+    r_o, ux_o, uy_o = O.moments(p, ref)
+    r_g, ux_g, uy_g = lat.moments()
+    u_o = np.hypot(ux_o, uy_o).max()
+    assert np.abs(ux_g - ux_o).max() / u_o < TOL32_U
+    assert np.abs(uy_g - uy_o).max() / u_o < TOL32_U
+    assert rel(r_g, r_o) < 1e-6
+    lat.close()
+
+
+# ---------------------------------------------------------------- long runs
+
+def _oracle_rounding_floor(make_p, f_init, nsteps, lams=(3.0, 0.7, 5.0, 1.3, 0.37, 2.2, 7.1)):
+    """FP64 rounding floor of the oracle's ux on a run: f -> lam f,
+    F -> lam F, rho0 -> lam rho0 leaves u unchanged in exact arithmetic (the
+    step is homogeneous of degree one), so the spread over lam is rounding
+    alone."""
+    base = None
+    worst = 0.0
+    for lam in (1.0,) + tuple(lams):
+        p = make_p(lam)
+        _, ux, _ = O.moments(p, O.run(p, lam * f_init(p), nsteps))
+        if base is None:
+            base = ux
+        else:
+            worst = max(worst, rel(ux, base))
+    return worst
+
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+def test_poiseuille_32x16_20000_steps(coll):
+    """nx 32, ny 16, a 0.5, nu 0.1, Fx 1e-6: u is ~8e-5, so an FP64 rounding
+    difference of one ulp of the O(0.1) populations is ~2e-12 of max |u|.
+    Populations must agree to 1e-12; the velocity to 1e-12 or, if larger,
+    three times the oracle's own rounding spread on this run (the GPU-oracle
+    difference adds two independent rounding walks)."""
+    nx, ny, a, cs2, nu, Fx = 32, 16, 0.5, 0.16, 0.1, 1e-6
+    tau = nu / cs2 + 0.5
+    rates = O.paper_rates(tau)
+
+    def make_p(lam=1.0):
+        return O.make_params(nx, ny, a, cs2, rates, force=(lam * Fx, 0), bc=(0, 0, 1, 1),
+                             collision=coll, rho0=lam)
+
+    p = make_p()
+    lat = L.Lattice(nx, ny, a, rates, bc_types=(0, 0, 1, 1), cs2=cs2, force=(Fx, 0),
+                    collision=coll)
+    lat.set_fields()
+    lat.step(20000)
+    ref = O.run(p, O.init(p), 20000)
+    assert rel(lat.get_populations(), ref) < TOL64
+    r_o, ux_o, uy_o = O.moments(p, ref)
+    r_g, ux_g, uy_g = lat.moments()
+    floor = _oracle_rounding_floor(make_p, lambda q: O.init(make_p()), 20000)
+    print("oracle rounding floor on u:", floor, "gpu vs oracle:", rel(ux_g, ux_o), flush=True)
+    assert rel(ux_g, ux_o) < max(TOL64, 3 * floor)
+    assert np.abs(uy_g).max() < 1e-14 and np.abs(uy_o).max() < 1e-14  # zero up to rounding
+    assert rel(r_g, r_o) < TOL64
+    H = ny * a
+    U = Fx * (H / 2) ** 2 / (2 * nu)
+    y = (np.arange(ny) + 0.5) * a
+    ua = U * (1 - (y - H / 2) ** 2 / (H / 2) ** 2)
+    assert np.sqrt(((ux_g[:, 0] - ua) ** 2).sum() / (ua ** 2).sum()) < 1e-2
+    lat.close()
+
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+def test_cavity_2000_steps(coll):
+    """Re 400 cavity, a 0.5, cs2 0.04 (the paper's choice for low tau at
+    a = 0.5, Table 3), tau 0.7."""
+    nx, ny, a, cs2, U = 64, 128, 0.5, 0.04, 0.05
+    nu = U * nx / 400.0
+    rates = O.paper_rates(nu / cs2 + 0.5)
+    bc, uw = (1, 1, 1, 2), ((0, 0), (0, 0), (0, 0), (U, 0))
+    p = O.make_params(nx, ny, a, cs2, rates, bc=bc, u_wall=uw, collision=coll)
+    lat = L.Lattice(nx, ny, a, rates, bc_types=bc, u_wall=uw, cs2=cs2, collision=coll)
+    lat.set_fields()
+    lat.step(2000)
+    ref = O.run(p, O.init(p), 2000)
+    r_o, ux_o, uy_o = O.moments(p, ref)
+    r_g, ux_g, uy_g = lat.moments()
+    assert rel(ux_g, ux_o) < TOL64 and rel(uy_g, uy_o) < TOL64 and rel(r_g, r_o) < TOL64
+    lat.close()
+
+
+# ---------------------------------------------------------------- full size
+
+def _sampled_check(p, lat, f_before, tol, seed=0, nsamp=48):
+    """After one GPU step from f_before, compare sampled nodes (edges and
+    corners included) with the oracle evaluated node by node."""
+    g = np.random.default_rng(seed)
+    nx, ny = p.nx, p.ny
+    pts = {(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1), (63, 1), (64, ny - 2),
+           (nx // 2, ny // 2)}
+    while len(pts) < nsamp:
+        pts.add((int(g.integers(nx)), int(g.integers(ny))))
+    got = lat.get_populations()
+    worst = 0.0
+    scale = np.abs(f_before).max()
+    for i, j in sorted(pts):
+        ref = O.step_node(p, f_before, i, j)
+        worst = max(worst, np.abs(got[:, j, i] - ref).max() / scale)
+    assert worst < tol
+    return worst
+
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+def test_full_size_cavity_512x1024_sampled(coll):
+    """The benchmark's cavity grid in its launch configuration."""
+    nx, ny, a, cs2, U = 512, 1024, 0.5, 0.16, 0.05
+    nu = U * nx / 1000.0
+    rates = O.paper_rates(nu / cs2 + 0.5)
+    bc, uw = (1, 1, 1, 2), ((0, 0), (0, 0), (0, 0), (U, 0))
+    p = O.make_params(nx, ny, a, cs2, rates, bc=bc, u_wall=uw, collision=coll)
+    for prec, tol in ((L.LBM_FP64, TOL64), (L.LBM_FP32_DEV, 1e-6)):
+        announce("full cavity", coll, prec)
+        lat = L.Lattice(nx, ny, a, rates, bc_types=bc, u_wall=uw, cs2=cs2, collision=coll,
+                        precision=prec)
+        rho, ux, uy = I.random_fields(41, nx, ny, u_amp=0.05)
+        lat.set_fields(rho, ux, uy)
+        lat.step(20)
+        f_before = lat.get_populations()
+        m_before = lat.sums()
+        lat.step(1)
+        _sampled_check(p, lat, f_before, tol)
+        m_after = lat.sums()
+        assert abs(m_after[0] - m_before[0]) / m_before[0] < (1e-14 if prec == 0 else 1e-7)
+        lat.close()
+
+
+def test_full_size_tgv_1024x2048_sampled_and_shape_invariance():
+    nx, ny, a, cs2 = 1024, 2048, 0.5, 0.16
+    rates = O.paper_rates(0.1 / cs2 + 0.5)
+    p = O.make_params(nx, ny, a, cs2, rates)
+    rho, ux, uy = I.taylor_green(nx, ny, a, 0.02, cs2)
+    outs = []
+    for rows in (0, 5):
+        lat = L.Lattice(nx, ny, a, rates, cs2=cs2, rows_per_wave=rows)
+        lat.set_fields(rho, ux, uy)
+        lat.step(10)
+        f_before = lat.get_populations()
+        lat.step(1)
+        if rows == 0:
+            _sampled_check(p, lat, f_before, TOL64, nsamp=32)
+        outs.append(lat.get_populations())
+        lat.close()
+    assert np.array_equal(outs[0], outs[1])

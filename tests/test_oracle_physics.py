@@ -161,3 +161,28 @@ def test_global_conservation(orc, coll):
     assert r1.sum() == pytest.approx(r0.sum(), rel=1e-14)
     assert (r1 * vx1).sum() - (r0 * vx0).sum() == pytest.approx(300 * n * F[0], rel=1e-9)
     assert (r1 * vy1).sum() - (r0 * vy0).sum() == pytest.approx(300 * n * F[1], rel=1e-9)
+
+
+def _cavity_blows_up(orc, Re, coll, nx=100, ny=200, a=0.5, cs2=0.1, U=0.2, steps=10000, chk=500):
+    nu = U * nx / Re
+    p = orc.make_params(nx, ny, a, cs2, orc.paper_rates(nu / cs2 + 0.5), bc=(1, 1, 1, 2),
+                        u_wall=((0, 0), (0, 0), (0, 0), (U, 0)), collision=coll)
+    f = orc.init(p)
+    for _ in range(steps // chk):
+        f = orc.run(p, f, chk)
+        _, ux, _ = orc.moments(p, f)
+        if not np.isfinite(ux).all() or np.abs(ux).max() > 1:
+            return True
+    return False
+
+
+@pytest.mark.slow
+def test_stability_bracket_of_table6(orc):
+    """Sec. 6, Table 6: at a = 0.5, U = 0.2, cs2 = 0.1 on 100 x 200 the maximum
+    stable Re is 6733 (RC) and 4591 (RNR).  Over 10^4 steps the oracle keeps
+    RC stable at Re 6000 while RNR blows up there, RNR is stable at Re 4000,
+    and RC blows up at Re 8000."""
+    assert not _cavity_blows_up(orc, 6000, orc.RC)
+    assert _cavity_blows_up(orc, 6000, orc.RNR)
+    assert not _cavity_blows_up(orc, 4000, orc.RNR)
+    assert _cavity_blows_up(orc, 8000, orc.RC)
