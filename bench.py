@@ -1,0 +1,283 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the fused rectangular-lattice CM-LBM step on one GPU.
+
+Default workload: lid-driven cavity on a square physical domain, nx 512 x
+ny 1024 nodes at aspect ratio r = dy/dx = 0.5, Re 1000, lid speed 0.05,
+FP32-deviation storage, RC collision (the raw-moment RNR variant is timed
+beside it).  A step is one collide-and-stream pass over the whole lattice;
+every `--check-every` steps the FP64 residual and conservation reductions run
+inside the timed region, as in a run to steady state.  Inputs (the cavity at
+rest, after the warm-up steps) are resident in HBM when timing starts.
+
+Prints ONE JSON line: MLUPS of the whole job, the roofline of the step kernel
+(algorithmic bytes per launch / mean launch time from HIP events on the
+library's stream), the HBM traffic measured by rocprofv3 counters (when
+profiles/ holds a measurement of the current kernel source) and the CPU
+oracle timed on a bounded sample on the host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_02119_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+WORKLOADS = {
+    # name: nx, ny, r, cs2, bc types, wall velocities, Re, lid/velocity scale
+    "cavity": dict(nx=512, ny=1024, r=0.5, cs2=0.16, bc=(1, 1, 1, 2), U=0.05, Re=1000.0),
+    "tgv": dict(nx=1024, ny=2048, r=0.5, cs2=0.16, bc=(0, 0, 0, 0), U=0.02, nu=0.1),
+    "shear": dict(nx=2048, ny=8192, r=0.25, cs2=0.04, bc=(0, 0, 0, 0), U=0.04, nu=1e-4),
+}
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def setup(name, precision, collision, rows=0):
+    from paper_2103_02119_amd import inputs as I
+    from paper_2103_02119_amd import lbm as L
+
+    w = WORKLOADS[name]
+    nx, ny, r, cs2 = w["nx"], w["ny"], w["r"], w["cs2"]
+    nu = w["U"] * nx / w["Re"] if "Re" in w else w["nu"]
+    tau = nu / cs2 + 0.5
+    rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
+    uw = ((0, 0), (0, 0), (0, 0), (w["U"], 0)) if name == "cavity" else ((0, 0),) * 4
+    lat = L.Lattice(nx, ny, r, rates, bc_types=w["bc"], u_wall=uw, cs2=cs2,
+                    collision=collision, precision=precision, rows_per_wave=rows)
+    if name == "cavity":
+        lat.set_fields(*I.cavity_rest(nx, ny))
+    elif name == "tgv":
+        lat.set_fields(*I.taylor_green(nx, ny, r, w["U"], cs2))
+    else:
+        lat.set_fields(*I.shear_layer(nx, ny, r, u0=w["U"]))
+    return lat, dict(nx=nx, ny=ny, r=r, cs2=cs2, tau=tau, nu=nu)
+
+
+def time_steps(lat, steps, check_every, chunk):
+    """Times `steps` steps issued `chunk` launches at a time (one C-level
+    loop per chunk), each chunk bracketed by HIP events on torch's current
+    stream (the stream the library enqueues on); the FP64 residual and sums
+    run every `check_every` steps.  Returns the wall time, the per-launch
+    kernel times from the events and the first step at which a reduction
+    reported a non-finite field (None if none did)."""
+    import torch
+
+    from paper_2103_02119_amd import lbm as L
+
+    s = torch.cuda.current_stream()
+    nchunks = (steps + chunk - 1) // chunk
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(nchunks)]
+    sizes = []
+    blew_up = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for c in range(nchunks):
+        n = min(chunk, steps - done)
+        ev[c][0].record(s)
+        lat.step(n)
+        ev[c][1].record(s)
+        sizes.append(n)
+        done += n
+        if check_every and done % check_every == 0 and blew_up is None:
+            try:
+                lat.residual()
+                lat.sums()
+            except L.LbmError as e:
+                if e.code != L.LBM_E_UNSTABLE:
+                    raise
+                blew_up = done
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_launch = [a.elapsed_time(b) / n for (a, b), n in zip(ev, sizes)]
+    return wall, per_launch, blew_up
+
+
+def cpu_baseline(name, collision, budget_s=10.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload (the same lattice advanced from the same start)."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2103_02119_amd import inputs as I
+
+    w = WORKLOADS[name]
+    nx, ny, r, cs2 = w["nx"], w["ny"], w["r"], w["cs2"]
+    nu = w["U"] * nx / w["Re"] if "Re" in w else w["nu"]
+    tau = nu / cs2 + 0.5
+    rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
+    uw = ((0, 0), (0, 0), (0, 0), (w["U"], 0)) if name == "cavity" else ((0, 0),) * 4
+    p = O.make_params(nx, ny, r, cs2, rates, bc=w["bc"], u_wall=uw, collision=collision)
+    if name == "cavity":
+        f = O.init(p, *I.cavity_rest(nx, ny))
+    elif name == "tgv":
+        f = O.init(p, *I.taylor_green(nx, ny, r, w["U"], cs2))
+    else:
+        f = O.init(p, *I.shear_layer(nx, ny, r, u0=w["U"]))
+    f = O.run(p, f, 1)  # first-touch / page-in
+    steps, t = 0, 0.0
+    chunk = 2
+    while t < budget_s:
+        t0 = time.perf_counter()
+        f = O.run(p, f, chunk)
+        t += time.perf_counter() - t0
+        steps += chunk
+    assert np.isfinite(f).all()
+    return dict(value=round(nx * ny * steps / t / 1e6, 3), unit="MLUPS", cores=O.max_threads(),
+                kind="oracle",
+                sample=f"{name} {nx}x{ny} r={r}, FP64 oracle, {steps} steps ({t:.1f} s) "
+                       f"from the same start, {'RC' if collision == 0 else 'RNR'}")
+
+
+def copy_probe(nbytes=1 << 30, reps=20):
+    """Plain device copy of a known size (counter calibration and the
+    achievable HBM bandwidth)."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes": nbytes, "read_plus_write_GBs": round(2 * nbytes / ms / 1e6, 1),
+                      "ms": round(ms, 4)}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cavity")
+    ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--chunk", type=int, default=10, help="launches per host call")
+    ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0 = automatic)")
+    ap.add_argument("--no-rnr", action="store_true", help="skip the RNR side-by-side timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the lattice step shards by slabs "
+              "with halo exchange (see the design notes), which is not built here.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2103_02119_amd import lbm as L
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+        return
+    prec = L.LBM_FP32_DEV if args.precision == "fp32dev" else L.LBM_FP64
+    bytes_per_lu = 72 if prec == L.LBM_FP32_DEV else 144
+
+    lat, info = setup(args.workload, prec, L.LBM_RC, args.rows)
+    nodes = info["nx"] * info["ny"]
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    wall, kern, blew_up = time_steps(lat, args.steps, args.check_every, args.chunk)
+    try:
+        R = lat.residual()
+        sums = lat.sums()
+    except L.LbmError as e:
+        if e.code != L.LBM_E_UNSTABLE:
+            raise
+        R, sums = float("nan"), [float("nan")] * 3
+        blew_up = blew_up or args.warmup + args.steps
+    rows, wgs = lat.launch_shape()
+    lat.close()
+
+    rnr = None
+    if not args.no_rnr:
+        lat2, _ = setup(args.workload, prec, L.LBM_RNR, args.rows)
+        lat2.step(args.warmup)
+        wall2, kern2, _ = time_steps(lat2, args.steps, args.check_every, args.chunk)
+        lat2.close()
+        rnr = dict(mlups=round(nodes * args.steps / wall2 / 1e6, 1),
+                   kernel_us=round(1e3 * sum(kern2) / len(kern2), 3))
+
+    mlups = nodes * args.steps / wall / 1e6
+    kern_ms = sum(kern) / len(kern)
+    achieved = bytes_per_lu * nodes / (kern_ms * 1e-3) / 1e9
+    # HBM bytes per launch from the rocprofv3 counters recorded in profiles/,
+    # valid only for the kernel source they were measured on
+    traffic, traffic_ratio = None, None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        key = f"{args.workload}/{args.precision}"
+        if tr.get("kernel_sha") == kernel_sha() and key in tr.get("per_launch", {}):
+            traffic = tr["per_launch"][key]["bytes_per_launch"]
+            traffic_ratio = tr["per_launch"][key]["ratio"]
+
+    out = {
+        "metric": "MLUPS + % HBM roofline; time-to-steady-state warm-start vs cold",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == L.LBM_FP32_DEV else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload} {info['nx']}x{info['ny']} r={info['r']}"
+                        + (f" Re={WORKLOADS[args.workload]['Re']:g} lid={WORKLOADS[args.workload]['U']}"
+                           if args.workload == "cavity" else ""),
+            "collision": "RC (RNR beside it)",
+            "storage": "FP32 deviations f - w rho0" if prec == L.LBM_FP32_DEV else "FP64",
+            "cs2": info["cs2"], "tau": round(info["tau"], 6),
+            "residual_every": args.check_every,
+            "rows_per_wave": rows, "workgroups": wgs,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_over_algorithmic": traffic_ratio,
+            "algorithmic_bytes_per_launch": bytes_per_lu * nodes,
+            "kernel": "lbm::step_kernel",
+            "bytes_per_lu": bytes_per_lu,
+            "kernel_us": round(1e3 * kern_ms, 3),
+        },
+        "rnr": rnr,
+        "final_residual": R,
+        "mass": sums[0],
+        "nonfinite_at_step": blew_up,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, L.LBM_RC, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -96,7 +96,7 @@ void lbm_default_opts(lbm_opts *o);
 /* Device bytes of one population buffer (9 planes of ny rows, each row padded
  * to a multiple of 64 values) for the given precision.
  * Errors: LBM_E_INVAL for nx or ny < 3, a bad precision or a lattice whose
- * plane exceeds 2^31 values. */
+ * plane (one population, padded rows) exceeds 4 GiB. */
 int lbm_required_bytes(int nx, int ny, int precision, size_t *f_bytes);
 
 /* Creates a lattice of nx x ny nodes with aspect ratio r = a = dy/dx

@@ -87,7 +87,8 @@ extern "C" int lbm_required_bytes(int nx, int ny, int precision, size_t *f_bytes
     if (precision < LBM_FP64 || precision > LBM_FP64_DEV)
         return fail_ctx(nullptr, LBM_E_INVAL, "unknown precision %d", precision);
     const long long plane = static_cast<long long>(pitch_of(nx)) * ny;
-    if (plane > 0x7fffffffLL)
+    // node offsets inside a plane are 32-bit byte offsets in the kernels
+    if (plane * static_cast<long long>(value_bytes(precision)) > 0xffffffffLL)
         return fail_ctx(nullptr, LBM_E_INVAL, "lattice too large: %lld values per plane", plane);
     *f_bytes = static_cast<size_t>(9) * plane * value_bytes(precision);
     return LBM_OK;
@@ -144,15 +145,19 @@ static void fill_consts(const lbm_ctx *c, Consts<R> &K) {
     }
 }
 
+// Launch shape and store policy, from measurements on MI355X: a wavefront
+// marches 2 rows on lattices below ~1M nodes (FP32) where latency dominates,
+// 4 below ~4M and 8 above; stores are non-temporal once the two population
+// buffers are well beyond the 256 MB Infinity Cache.
 static void choose_launch(lbm_ctx *c) {
     Geometry &G = c->G;
     G.nseg = (c->nx + kWave - 1) / kWave;
+    const long long nodes = static_cast<long long>(c->nx) * c->ny;
     int rows = c->opts.rows_per_wave;
     if (rows <= 0) {
-        // aim at ~8192 wavefronts (32 per CU on 256 CUs), 4..32 rows each
-        const long long want = (static_cast<long long>(c->ny) * G.nseg + 8191) / 8192;
-        rows = 4;
-        while (rows < want && rows < 32) rows *= 2;
+        if (nodes < (1LL << 20) && c->prec == kFP32Dev) rows = 2;
+        else if (nodes < (1LL << 22)) rows = 4;
+        else rows = 8;
     }
     if (rows > kMaxRows) rows = kMaxRows;
     if (rows > c->ny) rows = c->ny;
@@ -161,6 +166,7 @@ static void choose_launch(lbm_ctx *c) {
     G.ntile = G.nseg * G.nchunk;
     G.nblocks = (G.ntile + kWavesPerBlock - 1) / kWavesPerBlock;
     G.xcd_remap = (G.nblocks % 8 == 0) ? 1 : 0;
+    G.nt_store = 2.0 * static_cast<double>(c->f_bytes) > 512.0 * 1024 * 1024 ? 1 : 0;
 }
 
 static int validate(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
@@ -260,6 +266,8 @@ extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const
     G.plane = static_cast<long long>(G.pitch) * ny;
     for (int f = 0; f < 4; ++f) G.bc[f] = bc->type[f];
     G.corr = o.corrections ? 1 : 0;
+    G.buf_ok = need < 0xffffffffULL ? 1 : 0;
+    c->f_bytes = need;
     choose_launch(c);
     fill_consts(c, c->Kd);
     fill_consts(c, c->Kf);

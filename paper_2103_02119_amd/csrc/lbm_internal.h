@@ -42,6 +42,8 @@ struct Geometry {
     int xcd_remap;           // 1: contiguous tiles per XCD (nblocks % 8 == 0)
     int bc[4];               // Bc per face
     int corr;                // 1: Eq. 23-27 corrections on
+    int buf_ok;              // 1: a population buffer is below 4 GiB (buffer addressing)
+    int nt_store;            // 1: non-temporal population stores (buffers exceed the MALL)
     long long plane;         // pitch * ny
 };
 

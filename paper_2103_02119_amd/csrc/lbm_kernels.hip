@@ -112,16 +112,85 @@ __device__ __forceinline__ void load_node(const S *__restrict__ src, const Geome
     }
 }
 
-// Interior node (1 <= x <= nx-2, 1 <= j <= ny-2): no wrap, no wall.
+// Buffer resources: a 128-bit descriptor held in scalar registers (base,
+// byte range, data format 32) plus a 32-bit per-lane byte offset.  Accesses
+// past the range read 0 / are dropped by the hardware instead of faulting.
+constexpr int kBufFlags = 0x00020000;
+// cache-policy bits of a non-temporal store (used when the two population
+// buffers do not fit the Infinity Cache, so the stores need not stay there)
+constexpr int kStoreNT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0),
+                                             static_cast<int>(bytes), kBufFlags);
+}
+__device__ __forceinline__ float buf_load(float *, __amdgpu_buffer_rsrc_t r, uint32_t off,
+                                          uint32_t soff) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), static_cast<int>(soff), 0));
+}
+__device__ __forceinline__ double buf_load(double *, __amdgpu_buffer_rsrc_t r, uint32_t off,
+                                           uint32_t soff) {
+    return __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), static_cast<int>(soff), 0));
+}
+template <int AUX>
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off,
+                                          uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, static_cast<int>(off),
+                                          static_cast<int>(soff), AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t off,
+                                          uint32_t soff) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, static_cast<int>(off),
+                                          static_cast<int>(soff), AUX);
+}
+
+// Interior node (1 <= x <= nx-2, 1 <= j <= ny-2): no wrap, no wall.  One
+// descriptor covers the nine planes; the plane and row shift of each
+// direction is a wavefront-uniform scalar offset, the column shift an
+// immediate, so the only per-lane address is one 32-bit byte offset per row.
+// Needs the whole buffer below 4 GiB (Geometry::buf_ok).
 template <typename S, typename R, bool PULL>
 __device__ __forceinline__ void load_interior(const S *__restrict__ src, const Geometry &G,
                                               int j, int x, R (&f)[9]) {
-    const long long P = G.plane;
-    const S *q = src + static_cast<long long>(j) * G.pitch + x;
+    constexpr uint32_t B = sizeof(S);
+    const uint32_t pb = static_cast<uint32_t>(G.plane) * B;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, 9u * pb);
+    // byte offset of (x - 1, j): column shifts become immediates 0, B, 2B
+    const uint32_t obm = static_cast<uint32_t>(j * G.pitch + x - 1) * B;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int off = PULL ? -(cy_of(k) * G.pitch + cx_of(k)) : 0;
-        f[k] = static_cast<R>(q[k * P + off]);
+        const int cx = PULL ? cx_of(k) : 0, cy = PULL ? cy_of(k) : 0;
+        const uint32_t soff = static_cast<uint32_t>(k) * pb -
+                              static_cast<uint32_t>(cy * G.pitch) * B;
+        f[k] = static_cast<R>(buf_load(static_cast<S *>(nullptr), rs, obm + (1 - cx) * B, soff));
+    }
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store_node(S *__restrict__ dst, const Geometry &G, int j, int x,
+                                           const R (&o)[9]) {
+    if (G.buf_ok) {
+        constexpr uint32_t B = sizeof(S);
+        const uint32_t pb = static_cast<uint32_t>(G.plane) * B;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(dst, 9u * pb);
+        const uint32_t ob = static_cast<uint32_t>(j * G.pitch + x) * B;
+        if (G.nt_store) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                buf_store<kStoreNT>(static_cast<S>(o[k]), rs, ob, static_cast<uint32_t>(k) * pb);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                buf_store<0>(static_cast<S>(o[k]), rs, ob, static_cast<uint32_t>(k) * pb);
+        }
+    } else {
+        S *q = dst + static_cast<long long>(j) * G.pitch + x;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) q[k * G.plane] = static_cast<S>(o[k]);
     }
 }
 
@@ -147,9 +216,18 @@ __device__ __forceinline__ void inv1d(R k0, R k1, R k2, R v, R v2, R &p0, R &pp,
 // Both add the corrections of Eq. 23-27 with the strain rate of Eq. 37-38.
 // HU: omega_6 = omega_7 = omega_8 = 1 (the paper's setting), so the third-
 // and fourth-order pre-collision moments are not needed.
-template <typename R, bool DEV, int COLL, bool HU>
-__device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
-                                        const Consts<R> &K, R (&o)[9]) {
+// The work is split in two phases so that a step kernel can run the first
+// (which does not need the density gradient) while the loads of the
+// neighbouring row are still in flight.
+template <typename R>
+struct Pre {
+    R r00, rho, irho, ux, uy, vy, vy2, ux2, uy2, uxuy;
+    R N3, N4, N5, Q3, Q4, k20, k10;
+};
+
+template <typename R, bool DEV, int COLL>
+__device__ __forceinline__ Pre<R> collide_pre(const R (&p)[9], const Consts<R> &K) {
+    Pre<R> q;
     // x-sums of the three cy rows; (cx = 0, +1, -1) is (0,1,3), (2,5,6), (4,8,7)
     const R s0z = p[0] + p[1] + p[3], s1z = p[1] - p[3], s2z = p[1] + p[3];
     const R s0p = p[2] + p[5] + p[6], s1p = p[5] - p[6], s2p = p[5] + p[6];
@@ -163,49 +241,62 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
     const R r11 = s1p - s1m;
     // macroscopic fields, rho u = sum f e + F/2
     const R rr = DEV ? K.rr : R(0);
-    const R rho = rr + r00;
-    const R irho = R(1) / rho;
-    const R ux = (r10 + K.hFx) * irho;
-    const R uy = (K.a * r01 + K.hFy) * irho;
-    const R ux2 = ux * ux, uy2 = uy * uy, uxuy = ux * uy;
-
+    q.r00 = r00;
+    q.rho = rr + r00;
+    q.irho = R(1) / q.rho;
+    q.ux = (r10 + K.hFx) * q.irho;
+    q.uy = (K.a * r01 + K.hFy) * q.irho;
+    q.ux2 = q.ux * q.ux;
+    q.uy2 = q.uy * q.uy;
+    q.uxuy = q.ux * q.uy;
+    const R ux = q.ux, uy = q.uy, ux2 = q.ux2, uy2 = q.uy2;
     // second-order non-equilibrium parts N3, N4, N5 (f level, paper basis)
     // and the raw ones Q3, Q4 of Eq. 34-35 used by the strain rate
-    R N3, N4, N5, Q3, Q4;
-    R vy = R(0), vy2 = R(0), k20 = R(0), k10 = R(0);
     if (COLL == kRC) {
-        vy = uy * K.inv_a;  // velocity in units of a
-        vy2 = vy * vy;
-        k20 = r20 - R(2) * ux * r10 + ux2 * r00;             // sum p (cx-ux)^2
-        const R k02 = r02 - R(2) * vy * r01 + vy2 * r00;     // sum p (cy-vy)^2
-        k10 = r10 - ux * r00;
-        const R k11 = (r11 - ux * r01) - vy * k10;           // sum p (cx-ux)(cy-vy)
+        q.vy = uy * K.inv_a;  // velocity in units of a
+        q.vy2 = q.vy * q.vy;
+        q.k20 = r20 - R(2) * ux * r10 + ux2 * r00;            // sum p (cx-ux)^2
+        const R k02 = r02 - R(2) * q.vy * r01 + q.vy2 * r00;  // sum p (cy-vy)^2
+        q.k10 = r10 - ux * r00;
+        const R k11 = (r11 - ux * r01) - q.vy * q.k10;        // sum p (cx-ux)(cy-vy)
         const R ak02 = K.a2 * k02;
-        N3 = (k20 + ak02) - R(2) * K.s * r00 + rr * (ux2 + uy2);
-        N4 = (k20 - ak02) + rr * (ux2 - uy2);
-        N5 = K.a * k11 + rr * uxuy;
-        Q3 = N3 - (ux * K.Fx + uy * K.Fy);
-        Q4 = N4 - (ux * K.Fx - uy * K.Fy);
+        q.N3 = (q.k20 + ak02) - R(2) * K.s * r00 + rr * (ux2 + uy2);
+        q.N4 = (q.k20 - ak02) + rr * (ux2 - uy2);
+        q.N5 = K.a * k11 + rr * q.uxuy;
+        q.Q3 = q.N3 - (ux * K.Fx + uy * K.Fy);
+        q.Q4 = q.N4 - (ux * K.Fx - uy * K.Fy);
     } else {
+        q.vy = R(0);
+        q.vy2 = R(0);
+        q.k20 = R(0);
+        q.k10 = R(0);
         const R ar02 = K.a2 * r02;
-        N3 = (r20 + ar02) - R(2) * K.s * r00 - rho * (ux2 + uy2);
-        N4 = (r20 - ar02) - rho * (ux2 - uy2);
-        N5 = K.a * r11 - rho * uxuy;
-        Q3 = N3;
-        Q4 = N4;
+        q.N3 = (r20 + ar02) - R(2) * K.s * r00 - q.rho * (ux2 + uy2);
+        q.N4 = (r20 - ar02) - q.rho * (ux2 - uy2);
+        q.N5 = K.a * r11 - q.rho * q.uxuy;
+        q.Q3 = q.N3;
+        q.Q4 = q.N4;
     }
+    return q;
+}
 
+template <typename R, bool DEV, int COLL, bool HU>
+__device__ __forceinline__ void collide_post(const R (&p)[9], const Pre<R> &q, R gx, R gy,
+                                             int corr, const Consts<R> &K, R (&o)[9]) {
+    const R rr = DEV ? K.rr : R(0);
+    const R rho = q.rho, ux = q.ux, uy = q.uy, ux2 = q.ux2, uy2 = q.uy2, uxuy = q.uxuy;
+    const R r00 = q.r00;
     // local strain rate (Eq. 37-38, coefficients Eq. 40 divided by rho) and
     // the corrections (Eq. 23-26; Eq. 27: none on m_5)
     R del3 = R(0), del4 = R(0);
     if (corr) {
         const R tx = K.e1 * ux * gx;  // B3 d_x rho = C3 d_x rho
         const R ty = K.e2 * uy * gy;  // B4 d_y rho = -C4 d_y rho
-        const R M3 = Q3 - tx - ty;
-        const R M4 = Q4 - tx + ty;
+        const R M3 = q.Q3 - tx - ty;
+        const R M4 = q.Q4 - tx + ty;
         const R b1 = K.b1c + R(1.5) * ux2, b2 = K.b2c + R(1.5) * uy2;
         const R c1 = K.c1c + R(1.5) * ux2, c2 = K.c2c - R(1.5) * uy2;
-        const R idet = irho / (b1 * c2 - c1 * b2);
+        const R idet = q.irho / (b1 * c2 - c1 * b2);
         const R X = (c2 * M3 - b2 * M4) * idet;  // d ux / dx
         const R Y = (b1 * M4 - c1 * M3) * idet;  // d uy / dy
         const R t1 = K.q1 * (rho * X + ux * gx);
@@ -223,22 +314,27 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
         D0 = r00;
         D1 = K.hFx + rr * ux;  // relaxed first central moment = F/2 for any omega
         D2 = K.hFy + rr * uy;
-        D3 = R(2) * K.s * r00 - rr * (ux2 + uy2) + K.om[3] * N3 + K.w[3] * del3;
-        D4 = -rr * (ux2 - uy2) + K.om[4] * N4 + K.w[4] * del4;
-        D5 = -rr * uxuy + K.om[5] * N5;
+        D3 = R(2) * K.s * r00 - rr * (ux2 + uy2) + K.om[3] * q.N3 + K.w[3] * del3;
+        D4 = -rr * (ux2 - uy2) + K.om[4] * q.N4 + K.w[4] * del4;
+        D5 = -rr * uxuy + K.om[5] * q.N5;
         if (HU) {
             D6 = rr * sux2 * uy;
             D7 = rr * ux * suy2;
             D8 = K.s2 * r00 - rr * (K.s * (ux2 + uy2) + ux2 * uy2);
         } else {
+            const R s1p = p[5] - p[6], s2p = p[5] + p[6];
+            const R s1m = p[8] - p[7], s2m = p[8] + p[7];
+            const R s0p = p[2] + p[5] + p[6], s0m = p[4] + p[8] + p[7];
+            const R r01 = s0p - s0m, r02 = s0p + s0m, r11 = s1p - s1m;
             const R r21 = s2p - s2m, r12 = s1p + s1m, r22 = s2p + s2m;
+            const R vy = q.vy, vy2 = q.vy2;
             const R x21 = r21 - R(2) * ux * r11 + ux2 * r01;  // sum p (cx-ux)^2 cy
             const R x11 = r11 - ux * r01;                     // sum p (cx-ux) cy
             const R x12 = r12 - ux * r02;                     // sum p (cx-ux) cy^2
             const R x22 = r22 - R(2) * ux * r12 + ux2 * r02;  // sum p (cx-ux)^2 cy^2
-            const R k21 = x21 - vy * k20;
-            const R k12 = x12 - R(2) * vy * x11 + vy2 * k10;
-            const R k22 = x22 - R(2) * vy * x21 + vy2 * k20;
+            const R k21 = x21 - vy * q.k20;
+            const R k12 = x12 - R(2) * vy * x11 + vy2 * q.k10;
+            const R k22 = x22 - R(2) * vy * x21 + vy2 * q.k20;
             const R M6 = K.a * k21 - rr * sux2 * uy;
             const R M7 = K.a2 * k12 - rr * ux * suy2;
             const R M8 = K.a2 * k22 + rr * sux2 * suy2;
@@ -254,12 +350,14 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
         const R phi6 = Fy * ux2 + R(2) * Fx * uxuy;
         const R phi7 = Fx * uy2 + R(2) * Fy * uxuy;
         const R phi8 = R(2) * (Fx * ux * uy2 + Fy * uy * ux2);
+        const R s0p = p[2] + p[5] + p[6], s0m = p[4] + p[8] + p[7];
+        const R s1z = p[1] - p[3], s1p = p[5] - p[6], s1m = p[8] - p[7];
         D0 = r00;
-        D1 = r10 + Fx;  // momentum gains F for any omega_1, omega_2
-        D2 = K.a * r01 + Fy;
-        D3 = R(2) * K.s * r00 + rho * (ux2 + uy2) + K.om[3] * N3 + K.w[3] * del3 + K.sw[3] * phi3;
-        D4 = rho * (ux2 - uy2) + K.om[4] * N4 + K.w[4] * del4 + K.sw[4] * phi4;
-        D5 = rho * uxuy + K.om[5] * N5 + K.sw[5] * phi5;
+        D1 = (s1z + s1p + s1m) + Fx;  // momentum gains F for any omega_1, omega_2
+        D2 = K.a * (s0p - s0m) + Fy;
+        D3 = R(2) * K.s * r00 + rho * (ux2 + uy2) + K.om[3] * q.N3 + K.w[3] * del3 + K.sw[3] * phi3;
+        D4 = rho * (ux2 - uy2) + K.om[4] * q.N4 + K.w[4] * del4 + K.sw[4] * phi4;
+        D5 = rho * uxuy + K.om[5] * q.N5 + K.sw[5] * phi5;
         const R e6 = rho * uy * sux2, e7 = rho * ux * suy2;
         const R e8x = r00 * K.s2 + rho * (K.s * (ux2 + uy2) + ux2 * uy2);  // eq8 - rr s^2
         if (HU) {
@@ -267,6 +365,7 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
             D7 = e7 + R(0.5) * phi7;
             D8 = e8x + R(0.5) * phi8;
         } else {
+            const R s2p = p[5] + p[6], s2m = p[8] + p[7];
             const R r21 = s2p - s2m, r12 = s1p + s1m, r22 = s2p + s2m;
             const R N6 = K.a * r21 - e6;
             const R N7 = K.a2 * r12 - e7;
@@ -284,7 +383,7 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
     const R t12 = D7 * K.inv_a2, t22 = D8 * K.inv_a2;
     // RC: they are central moments about (ux, vy); RNR: raw (about 0)
     const R sx = (COLL == kRC) ? ux : R(0), sx2 = (COLL == kRC) ? ux2 : R(0);
-    const R sy = (COLL == kRC) ? vy : R(0), sy2 = (COLL == kRC) ? vy2 : R(0);
+    const R sy = (COLL == kRC) ? q.vy : R(0), sy2 = (COLL == kRC) ? q.vy2 : R(0);
     // y stage for m = 0, 1, 2
     R y00, y0p, y0m, y10, y1p, y1m, y20, y2p, y2m;
     inv1d(D0, t01, t02, sy, sy2, y00, y0p, y0m);
@@ -296,80 +395,97 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
     inv1d(y0m, y1m, y2m, sx, sx2, o[4], o[8], o[7]);
 }
 
+template <typename R, bool DEV, int COLL, bool HU>
+__device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
+                                        const Consts<R> &K, R (&o)[9]) {
+    const Pre<R> q = collide_pre<R, DEV, COLL>(p, K);
+    collide_post<R, DEV, COLL, HU>(p, q, gx, gy, corr, K, o);
+}
+
 // ------------------------------------------------------------ step kernel
 
-template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU>
-__global__ void __launch_bounds__(kBlock)
-step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, const Consts<R> K) {
-    const int lane = threadIdx.x & (kWave - 1);
-    int b = blockIdx.x;
-    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous run of tiles so neighbouring segments share its L2
-    if (G.xcd_remap) b = (b & 7) * (G.nblocks >> 3) + (b >> 3);
-    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
-    if (tile >= G.ntile) return;
-    const int seg = tile % G.nseg;
-    const int chunk = tile / G.nseg;
-    const int x0 = seg * kWave;
-    const int j0 = chunk * G.rows;
-    const int j1 = min(j0 + G.rows, G.ny);
-    const int xlast = min(x0 + kWave - 1, G.nx - 1);
-    const int xraw = x0 + lane;
-    const bool active = xraw < G.nx;
-    const int x = min(xraw, G.nx - 1);
+// Marches one wavefront tile (64 columns x rows j0..j1-1), keeping the
+// populations of rows j .. j+D in registers: row j is collided while rows
+// j+2 .. j+D are in flight (D = 3 for FP32 storage, 2 for FP64 where the
+// registers are scarcer).  GENERIC handles wrap-around and walls on every
+// load; the fast variant is used when every node the tile pulls is interior,
+// so it carries no boundary logic and no wall constants.  The halo columns'
+// populations arrive with the prologue and are summed only afterwards, so
+// the tile starts with a single latency round.
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU, bool GENERIC>
+__device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__ dst,
+                                      const Geometry &G, const Consts<R> &K, int lane, int j0,
+                                      int j1, int x0, int x, int xraw, int xlast, bool active,
+                                      bool wall_left, bool wall_right) {
+    constexpr int D = sizeof(S) == 4 ? 3 : 2;
     const ColInfo c = col_info(x, G);
-    const bool edge_cols = (x0 == 0) || (x0 + kWave >= G.nx);
-    const bool wall_left = (x0 == 0) && G.bc[kXmin] != kPeriodic;
-    const bool wall_right = (xlast == G.nx - 1) && G.bc[kXmax] != kPeriodic;
-
-    // halo pass: lane l gets rho at (x0 - 1, j0 + l) and (xlast + 1, j0 + l)
-    R hl = R(0), hr = R(0);
-    {
-        const RowInfo rh = row_info(min(j0 + lane, j1 - 1), G);
-        R f9[9];
-        if (!wall_left) {
-            load_node<S, R, PULL>(src, G, K, rh, col_info(x0 > 0 ? x0 - 1 : G.nx - 1, G), f9);
-            hl = sum9(f9);
-        }
-        if (!wall_right) {
-            load_node<S, R, PULL>(src, G, K, rh, col_info(xlast < G.nx - 1 ? xlast + 1 : 0, G), f9);
-            hr = sum9(f9);
-        }
-    }
-
     auto load_row = [&](int jj, R (&f9)[9]) {
-        if (!edge_cols && jj > 0 && jj < G.ny - 1)
-            load_interior<S, R, PULL>(src, G, jj, x, f9);
-        else
+        if (GENERIC)
             load_node<S, R, PULL>(src, G, K, row_info(jj, G), c, f9);
+        else
+            load_interior<S, R, PULL>(src, G, jj, x, f9);
+    };
+    // a row index that exists (wrapping periodically) or -1 beyond a wall
+    auto row_of = [&](int jj) -> int {
+        if (jj < G.ny) return jj;
+        return (GENERIC && G.bc[kYmax] != kPeriodic) ? -1 : jj - G.ny;
     };
 
-    // marching window: rho below (rb), populations and rho of the current row
-    R fc[9];
-    R rb;
-    const bool below = (j0 > 0) || G.bc[kYmin] == kPeriodic;
-    if (below) {
-        R f9[9];
-        load_row(j0 > 0 ? j0 - 1 : G.ny - 1, f9);
-        rb = sum9(f9);
-    }
-    load_row(j0, fc);
-    R rc = sum9(fc);
-    if (!below) rb = rc;  // wall: the missing neighbour's density is the node's own
-
-    for (int j = j0; j < j1; ++j) {
-        R fn[9];
-        R rn;
-        const bool above = (j + 1 < G.ny) || G.bc[kYmax] == kPeriodic;
-        if (above) {
-            load_row(j + 1 < G.ny ? j + 1 : 0, fn);
-            rn = sum9(fn);
-        } else {
+    // halo loads: lane l fetches the nodes at (x0 - 1, j0 + l) and (xlast + 1, j0 + l)
+    R hfl[9], hfr[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) fn[k] = R(0);
-            rn = rc;
+    for (int k = 0; k < 9; ++k) hfl[k] = hfr[k] = R(0);
+    {
+        const RowInfo rh = row_info(min(j0 + lane, j1 - 1), G);
+        if (!wall_left)
+            load_node<S, R, PULL>(src, G, K, rh, col_info(x0 > 0 ? x0 - 1 : G.nx - 1, G), hfl);
+        if (!wall_right)
+            load_node<S, R, PULL>(src, G, K, rh, col_info(xlast < G.nx - 1 ? xlast + 1 : 0, G), hfr);
+    }
+    // prologue: the ring row below and rows j0 .. j0 + D - 1
+    const bool below = !GENERIC || (j0 > 0) || G.bc[kYmin] == kPeriodic;
+    R fb[9];
+    R fr[D + 1][9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        fb[k] = R(0);
+#pragma unroll
+        for (int d = 0; d <= D; ++d) fr[d][k] = R(0);
+    }
+    if (below) load_row(j0 > 0 ? j0 - 1 : G.ny - 1, fb);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (GENERIC) {
+            const int jj = row_of(j0 + d);
+            if (j0 + d <= j1 && jj >= 0) load_row(jj, fr[d]);
+        } else {
+            load_row(min(j0 + d, j1), fr[d]);
         }
-        // left / right neighbour densities at the same time level
+    }
+    const R hl = wall_left ? R(0) : sum9(hfl);
+    const R hr = wall_right ? R(0) : sum9(hfr);
+    R rc = sum9(fr[0]);
+    R rb = below ? sum9(fb) : rc;  // wall: the missing neighbour's density is the node's own
+
+    // One row: issue the loads of row j + D into `nxt` (the array that held
+    // row j - 1), collide row j (`cur`) with the density of row j + 1 from
+    // `up`.  The loop is unrolled D + 1 times with the arrays' roles permuted,
+    // so no register that an in-flight load targets is ever copied (a copy
+    // would make the wavefront wait for every outstanding load).
+    auto row_step = [&](int j, R (&cur)[9], R (&up)[9], R (&nxt)[9]) {
+        if (GENERIC) {
+            const int jj = row_of(j + D);
+            if (j + D <= j1 && jj >= 0) load_row(jj, nxt);
+        } else {
+            // unconditional (the last rows re-read the cached ring row j1): a
+            // load inside a branch would make the wait counts collapse to a
+            // full drain where the paths join
+            load_row(min(j + D, j1), nxt);
+        }
+        const Pre<R> q = collide_pre<R, DEV, COLL>(cur, K);
+
+        // densities of the four neighbours at the same time level
+        const R rn = row_of(j + 1) >= 0 ? sum9(up) : rc;
         R rl = __shfl_up(rc, 1);
         R rgt = __shfl_down(rc, 1);
         const R hlj = readlane(hl, j - j0);
@@ -380,17 +496,60 @@ step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, co
         const R gy = (rn - rb) * K.half_inv_a;
 
         R out[9];
-        collide<R, DEV, COLL, HU>(fc, gx, gy, G.corr, K, out);
-        if (active) {
-            S *q = dst + static_cast<long long>(j) * G.pitch + xraw;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) q[k * G.plane] = static_cast<S>(out[k]);
-        }
+        collide_post<R, DEV, COLL, HU>(cur, q, gx, gy, G.corr, K, out);
+        if (active) store_node(dst, G, j, xraw, out);
         rb = rc;
         rc = rn;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) fc[k] = fn[k];
+    };
+    if constexpr (D == 3) {
+        for (int j = j0; j < j1; j += 4) {
+            row_step(j, fr[0], fr[1], fr[3]);
+            if (j + 1 < j1) row_step(j + 1, fr[1], fr[2], fr[0]);
+            if (j + 2 < j1) row_step(j + 2, fr[2], fr[3], fr[1]);
+            if (j + 3 < j1) row_step(j + 3, fr[3], fr[0], fr[2]);
+        }
+    } else {
+        for (int j = j0; j < j1; j += 3) {
+            row_step(j, fr[0], fr[1], fr[2]);
+            if (j + 1 < j1) row_step(j + 1, fr[1], fr[2], fr[0]);
+            if (j + 2 < j1) row_step(j + 2, fr[2], fr[0], fr[1]);
+        }
     }
+}
+
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU>
+__global__ void __launch_bounds__(kBlock)
+step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, const Consts<R> K) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int b = blockIdx.x;
+    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous run of tiles so neighbouring segments share its L2
+    if (G.xcd_remap) b = (b & 7) * (G.nblocks >> 3) + (b >> 3);
+    // the wavefront index is uniform across the wavefront; say so, so that all
+    // tile bookkeeping lives in scalar registers and branches are scalar
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int tile = b * kWavesPerBlock + wave;
+    if (tile >= G.ntile) return;
+    const int seg = tile % G.nseg;
+    const int chunk = tile / G.nseg;
+    const int x0 = seg * kWave;
+    const int j0 = chunk * G.rows;
+    const int j1 = min(j0 + G.rows, G.ny);
+    const int xlast = min(x0 + kWave - 1, G.nx - 1);
+    const int xraw = x0 + lane;
+    const bool active = xraw < G.nx;
+    const int x = min(xraw, G.nx - 1);
+    const bool wall_left = (x0 == 0) && G.bc[kXmin] != kPeriodic;
+    const bool wall_right = (xlast == G.nx - 1) && G.bc[kXmax] != kPeriodic;
+    // every pulled node (rows j0-1 .. j1, columns x0-1 .. x0+64) interior?
+    const bool interior =
+        G.buf_ok && (x0 > 0) && (x0 + kWave < G.nx) && (j0 >= 2) && (j1 <= G.ny - 2);
+    if (interior)
+        march<S, R, DEV, COLL, PULL, HU, false>(src, dst, G, K, lane, j0, j1, x0, x, xraw, xlast,
+                                                 active, wall_left, wall_right);
+    else
+        march<S, R, DEV, COLL, PULL, HU, true>(src, dst, G, K, lane, j0, j1, x0, x, xraw, xlast,
+                                                active, wall_left, wall_right);
 }
 
 template <typename S, typename R, bool DEV>

@@ -372,3 +372,21 @@ def test_full_size_tgv_1024x2048_sampled_and_shape_invariance():
         outs.append(lat.get_populations())
         lat.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec,tol", [(L.LBM_FP64, TOL64), (L.LBM_FP32_DEV, 1e-6)])
+def test_full_size_shear_layer_2048x8192_sampled(prec, tol):
+    """The 2048 x 8192, r = 0.25 doubly periodic shear layer: buffers beyond
+    the Infinity Cache (non-temporal stores), 8 rows per wavefront."""
+    nx, ny, a, cs2 = 2048, 8192, 0.25, 0.04
+    rates = O.paper_rates(1e-4 / cs2 + 0.5)
+    p = O.make_params(nx, ny, a, cs2, rates)
+    announce("full shear", prec)
+    lat = L.Lattice(nx, ny, a, rates, cs2=cs2, precision=prec)
+    assert lat.launch_shape()[0] == 8
+    lat.set_fields(*I.shear_layer(nx, ny, a))
+    lat.step(5)
+    f_before = lat.get_populations()
+    lat.step(1)
+    _sampled_check(p, lat, f_before, tol, nsamp=40)
+    lat.close()
