@@ -59,8 +59,10 @@ enum { LBM_RC = 0, LBM_RNR = 1 };
  *   LBM_FP64      populations f stored and collided in FP64;
  *   LBM_FP32_DEV  deviations g = f - w rho0 stored and collided in FP32
  *                 (w = rest-state equilibrium weights); reductions in FP64;
- *   LBM_FP64_DEV  the deviation algorithm in FP64 (a check of that algebra). */
-enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP64_DEV = 2 };
+ *   LBM_FP64_DEV  the deviation algorithm in FP64 (a check of that algebra);
+ *   LBM_FP32_DEV_F64  deviations stored in FP32 (FP32 traffic), collided in FP64
+ *                 (FP64 vector arithmetic runs at the unpacked FP32 rate on CDNA). */
+enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP64_DEV = 2, LBM_FP32_DEV_F64 = 3 };
 
 /* Boundary description.  x-min/x-max must both be periodic or both not; the
  * same for y-min/y-max.  u_wall[face] = (Ux, Uy) is used by
@@ -78,7 +80,7 @@ typedef struct {
     double force[2];   /* uniform body force (Fx, Fy), lattice units (Eq. 13) */
     double rho0;       /* reference density: wall density and deviation origin; 0 => 1 */
     int collision;     /* LBM_RC (default) or LBM_RNR */
-    int precision;     /* LBM_FP64 (default), LBM_FP32_DEV, LBM_FP64_DEV */
+    int precision;     /* LBM_FP64 (default), LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 */
     int corrections;   /* 1 (default): Eq. 23-27 corrections; 0: leave them out */
     int rows_per_wave; /* launch shape override (rows marched by one wavefront);
                           0 = automatic */

@@ -69,7 +69,7 @@ static int fail_ctx(lbm_ctx *ctx, int code, const char *fmt, ...) {
 
 static int pitch_of(int nx) { return (nx + kWave - 1) / kWave * kWave; }
 
-static size_t value_bytes(int prec) { return prec == kFP32Dev ? sizeof(float) : sizeof(double); }
+static size_t value_bytes(int prec) { return f32_storage(prec) ? sizeof(float) : sizeof(double); }
 
 extern "C" void lbm_default_opts(lbm_opts *o) {
     if (!o) return;
@@ -84,7 +84,7 @@ extern "C" void lbm_default_opts(lbm_opts *o) {
 extern "C" int lbm_required_bytes(int nx, int ny, int precision, size_t *f_bytes) {
     if (!f_bytes) return fail_ctx(nullptr, LBM_E_INVAL, "f_bytes is NULL");
     if (nx < 3 || ny < 3) return fail_ctx(nullptr, LBM_E_INVAL, "nx and ny must be >= 3");
-    if (precision < LBM_FP64 || precision > LBM_FP64_DEV)
+    if (precision < LBM_FP64 || precision > LBM_FP32_DEV_F64)
         return fail_ctx(nullptr, LBM_E_INVAL, "unknown precision %d", precision);
     const long long plane = static_cast<long long>(pitch_of(nx)) * ny;
     // node offsets inside a plane are 32-bit byte offsets in the kernels
@@ -191,7 +191,7 @@ static int validate(int nx, int ny, double r, const double *rates, const lbm_bc 
         return fail_ctx(nullptr, LBM_E_INVAL, "opposite faces must both be periodic or both not");
     if (o->collision != LBM_RC && o->collision != LBM_RNR)
         return fail_ctx(nullptr, LBM_E_INVAL, "unknown collision %d", o->collision);
-    if (o->precision < LBM_FP64 || o->precision > LBM_FP64_DEV)
+    if (o->precision < LBM_FP64 || o->precision > LBM_FP32_DEV_F64)
         return fail_ctx(nullptr, LBM_E_INVAL, "unknown precision %d", o->precision);
     if (!(o->rho0 > 0.0)) return fail_ctx(nullptr, LBM_E_INVAL, "rho0 must be > 0");
     if (!isfinite(o->force[0]) || !isfinite(o->force[1]))

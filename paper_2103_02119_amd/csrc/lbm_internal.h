@@ -14,7 +14,9 @@ constexpr int kMaxRows = 64;        // rows marched by one wavefront (halo pass 
 constexpr int kReduceBlock = 256;
 constexpr int kMaxPartials = 4096;  // per-block partial sums of the reductions
 
-enum Prec { kFP64 = 0, kFP32Dev = 1, kFP64Dev = 2 };
+enum Prec { kFP64 = 0, kFP32Dev = 1, kFP64Dev = 2, kFP32DevF64 = 3 };
+// populations stored as FP32 deviations (kFP32Dev, kFP32DevF64)
+__host__ __device__ constexpr bool f32_storage(int prec) { return prec == kFP32Dev || prec == kFP32DevF64; }
 enum Face { kXmin = 0, kXmax = 1, kYmin = 2, kYmax = 3 };
 enum Bc { kPeriodic = 0, kWall = 1, kMovingWall = 2 };
 enum Coll { kRC = 0, kRNR = 1 };

@@ -417,7 +417,7 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
                                       const Geometry &G, const Consts<R> &K, int lane, int j0,
                                       int j1, int x0, int x, int xraw, int xlast, bool active,
                                       bool wall_left, bool wall_right) {
-    constexpr int D = sizeof(S) == 4 ? 3 : 2;
+    constexpr int D = sizeof(R) == 4 ? 3 : 2;
     const ColInfo c = col_info(x, G);
     auto load_row = [&](int jj, R (&f9)[9]) {
         if (GENERIC)
@@ -584,6 +584,7 @@ hipError_t launch_step(int prec, int coll, bool pull, bool hu, const void *src, 
     case kFP64: return step_dispatch<double, double, false>(coll, pull, hu, src, dst, G, Kd, st);
     case kFP32Dev: return step_dispatch<float, float, true>(coll, pull, hu, src, dst, G, Kf, st);
     case kFP64Dev: return step_dispatch<double, double, true>(coll, pull, hu, src, dst, G, Kd, st);
+    case kFP32DevF64: return step_dispatch<float, double, true>(coll, pull, hu, src, dst, G, Kd, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -783,7 +784,7 @@ static int conv_blocks(const Geometry &G) {
 hipError_t launch_init_feq(int prec, void *dst, const double *rho, const double *ux,
                            const double *uy, const Geometry &G, const HostSide &H,
                            hipStream_t st) {
-    if (prec == kFP32Dev)
+    if (f32_storage(prec))
         hipLaunchKernelGGL(init_feq_kernel<float>, dim3(conv_blocks(G)), dim3(256), 0, st,
                            static_cast<float *>(dst), rho, ux, uy, G, H);
     else
@@ -794,7 +795,7 @@ hipError_t launch_init_feq(int prec, void *dst, const double *rho, const double 
 
 hipError_t launch_set_populations(int prec, void *dst, const double *f, const Geometry &G,
                                   const HostSide &H, hipStream_t st) {
-    if (prec == kFP32Dev)
+    if (f32_storage(prec))
         hipLaunchKernelGGL(set_pop_kernel<float>, dim3(conv_blocks(G)), dim3(256), 0, st,
                            static_cast<float *>(dst), f, G, H);
     else
@@ -807,7 +808,7 @@ hipError_t launch_get_populations(int prec, bool pull, const void *src, double *
                                   const Geometry &G, const Consts<double> &Kd,
                                   const Consts<float> &, const HostSide &H, hipStream_t st) {
     const dim3 grid(conv_blocks(G)), block(256);
-    if (prec == kFP32Dev) {
+    if (f32_storage(prec)) {
         const float *s = static_cast<const float *>(src);
         if (pull) hipLaunchKernelGGL((get_pop_kernel<float, true>), grid, block, 0, st, s, f, G, Kd, H);
         else hipLaunchKernelGGL((get_pop_kernel<float, false>), grid, block, 0, st, s, f, G, Kd, H);
@@ -823,7 +824,7 @@ hipError_t launch_moments(int prec, bool pull, const void *src, double *rho, dou
                           double *uy, const Geometry &G, const Consts<double> &Kd,
                           const Consts<float> &, const HostSide &H, hipStream_t st) {
     const dim3 grid(conv_blocks(G)), block(256);
-    if (prec == kFP32Dev) {
+    if (f32_storage(prec)) {
         const float *s = static_cast<const float *>(src);
         if (pull) hipLaunchKernelGGL((moments_kernel<float, true>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
         else hipLaunchKernelGGL((moments_kernel<float, false>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
@@ -840,7 +841,7 @@ hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, d
                        const HostSide &H, hipStream_t st) {
     const int nb = reduce_blocks(G);
     const dim3 grid(nb), block(kReduceBlock);
-    if (prec == kFP32Dev) {
+    if (f32_storage(prec)) {
         const float *s = static_cast<const float *>(src);
         if (pull) hipLaunchKernelGGL((sums_kernel<float, true>), grid, block, 0, st, s, partials, G, Kd, H);
         else hipLaunchKernelGGL((sums_kernel<float, false>), grid, block, 0, st, s, partials, G, Kd, H);
@@ -871,7 +872,7 @@ hipError_t launch_residual(int prec, bool pull_cur, const void *cur, bool pull_p
                            const Consts<double> &Kd, const Consts<float> &, const HostSide &H,
                            hipStream_t st) {
     const int nb = reduce_blocks(G);
-    if (prec == kFP32Dev)
+    if (f32_storage(prec))
         residual_dispatch<float>(pull_cur, static_cast<const float *>(cur), pull_prev,
                                  static_cast<const float *>(prev), partials, G, Kd, H, nb, st);
     else

@@ -23,7 +23,7 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 0,
 LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_MOVING_WALL = 0, 1, 2
 LBM_FACE_XMIN, LBM_FACE_XMAX, LBM_FACE_YMIN, LBM_FACE_YMAX = 0, 1, 2, 3
 LBM_RC, LBM_RNR = 0, 1
-LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV = 0, 1, 2
+LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
            "lbm_moments", "lbm_residual", "lbm_sums", "lbm_get_populations",

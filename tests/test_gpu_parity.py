@@ -2,7 +2,7 @@
 
 Bars (per field, max-norm relative to the oracle's max |value|):
   FP64 and FP64-deviation storage: 1e-12;
-  FP32-deviation storage: 1e-5 on velocity.
+  FP32-deviation storage (FP32 or FP64 collision arithmetic): 1e-5 on velocity.
 Inputs are seeded random near-equilibrium states (paper_2103_02119_amd.inputs)
 on grids that span several 64-column segments with a ragged tail, plus the
 degenerate shapes (3 x 3, one-column tails, one-row chunks)."""
@@ -159,7 +159,7 @@ def test_populations_roundtrip():
 
 # ---------------------------------------------------------------- reductions
 
-@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV, L.LBM_FP32_DEV_F64])
 @pytest.mark.parametrize("name", ["periodic", "cavity", "channel"])
 def test_sums_and_residual(name, prec):
     nx, ny = 150, 70
@@ -216,12 +216,13 @@ def test_first_step_residual_and_unstable_flag():
 
 # ---------------------------------------------------------------- FP32
 
+@pytest.mark.parametrize("prec", [L.LBM_FP32_DEV, L.LBM_FP32_DEV_F64])
 @pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp32_deviation_velocity(name, coll):
+def test_fp32_deviation_velocity(name, coll, prec):
     nx, ny = 150, 70
-    announce("fp32", name, coll)
-    p, lat = make(name, nx, ny, coll, L.LBM_FP32_DEV)
+    announce("fp32", name, coll, prec)
+    p, lat = make(name, nx, ny, coll, prec)
     f0 = random_state(p, seed=31)
     lat.set_populations(f0)
     lat.step(50)
@@ -339,7 +340,7 @@ def test_full_size_cavity_512x1024_sampled(coll):
     rates = O.paper_rates(nu / cs2 + 0.5)
     bc, uw = (1, 1, 1, 2), ((0, 0), (0, 0), (0, 0), (U, 0))
     p = O.make_params(nx, ny, a, cs2, rates, bc=bc, u_wall=uw, collision=coll)
-    for prec, tol in ((L.LBM_FP64, TOL64), (L.LBM_FP32_DEV, 1e-6)):
+    for prec, tol in ((L.LBM_FP64, TOL64), (L.LBM_FP32_DEV, 1e-6), (L.LBM_FP32_DEV_F64, 1e-6)):
         announce("full cavity", coll, prec)
         lat = L.Lattice(nx, ny, a, rates, bc_types=bc, u_wall=uw, cs2=cs2, collision=coll,
                         precision=prec)
@@ -374,7 +375,8 @@ def test_full_size_tgv_1024x2048_sampled_and_shape_invariance():
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("prec,tol", [(L.LBM_FP64, TOL64), (L.LBM_FP32_DEV, 1e-6)])
+@pytest.mark.parametrize("prec,tol", [(L.LBM_FP64, TOL64), (L.LBM_FP32_DEV, 1e-6),
+                                      (L.LBM_FP32_DEV_F64, 1e-6)])
 def test_full_size_shear_layer_2048x8192_sampled(prec, tol):
     """The 2048 x 8192, r = 0.25 doubly periodic shear layer: buffers beyond
     the Infinity Cache (non-temporal stores), 8 rows per wavefront."""
