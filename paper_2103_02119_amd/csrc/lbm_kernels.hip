@@ -219,6 +219,14 @@ __device__ __forceinline__ void inv1d(R k0, R k1, R k2, R v, R v2, R &p0, R &pp,
 // The work is split in two phases so that a step kernel can run the first
 // (which does not need the density gradient) while the loads of the
 // neighbouring row are still in flight.
+// rho x with rho = rr + r00 kept split in deviation mode, so that the
+// rounding of the density sum (see collide_pre) does not scale equilibrium
+// terms by a regionally constant factor
+template <bool DEV, typename R>
+__device__ __forceinline__ R rho_times(R rr, R r00, R x) {
+    return DEV ? rr * x + r00 * x : r00 * x;
+}
+
 template <typename R>
 struct Pre {
     R r00, rho, irho, ux, uy, vy, vy2, ux2, uy2, uxuy;
@@ -241,11 +249,28 @@ __device__ __forceinline__ Pre<R> collide_pre(const R (&p)[9], const Consts<R> &
     const R r11 = s1p - s1m;
     // macroscopic fields, rho u = sum f e + F/2
     const R rr = DEV ? K.rr : R(0);
+    const R jx = r10 + K.hFx, jy = K.a * r01 + K.hFy;
     q.r00 = r00;
     q.rho = rr + r00;
-    q.irho = R(1) / q.rho;
-    q.ux = (r10 + K.hFx) * q.irho;
-    q.uy = (K.a * r01 + K.hFy) * q.irho;
+    if (DEV && sizeof(R) == 4) {
+        // In FP32 the sum rr + r00 drops the low bits of the density
+        // deviation, and that rounding is the same over whole regions where
+        // the density varies slowly: u = j / rho would carry a regionally
+        // constant relative error, i.e. a momentum source or sink at every
+        // collision.  One Newton step against the unrounded density
+        // rr + r00 removes it (the residual j - u0 (rr + r00) is formed with
+        // the two parts of the density separately).
+        q.irho = __builtin_amdgcn_rcpf(q.rho);
+        const R ux0 = jx * q.irho, uy0 = jy * q.irho;
+        const R ex = __builtin_fmaf(-ux0, rr, jx) - ux0 * r00;
+        const R ey = __builtin_fmaf(-uy0, rr, jy) - uy0 * r00;
+        q.ux = __builtin_fmaf(ex, q.irho, ux0);
+        q.uy = __builtin_fmaf(ey, q.irho, uy0);
+    } else {
+        q.irho = R(1) / q.rho;
+        q.ux = jx * q.irho;
+        q.uy = jy * q.irho;
+    }
     q.ux2 = q.ux * q.ux;
     q.uy2 = q.uy * q.uy;
     q.uxuy = q.ux * q.uy;
@@ -271,9 +296,9 @@ __device__ __forceinline__ Pre<R> collide_pre(const R (&p)[9], const Consts<R> &
         q.k20 = R(0);
         q.k10 = R(0);
         const R ar02 = K.a2 * r02;
-        q.N3 = (r20 + ar02) - R(2) * K.s * r00 - q.rho * (ux2 + uy2);
-        q.N4 = (r20 - ar02) - q.rho * (ux2 - uy2);
-        q.N5 = K.a * r11 - q.rho * q.uxuy;
+        q.N3 = (r20 + ar02) - R(2) * K.s * r00 - rho_times<DEV>(rr, r00, ux2 + uy2);
+        q.N4 = (r20 - ar02) - rho_times<DEV>(rr, r00, ux2 - uy2);
+        q.N5 = K.a * r11 - rho_times<DEV>(rr, r00, q.uxuy);
         q.Q3 = q.N3;
         q.Q4 = q.N4;
     }
@@ -355,11 +380,12 @@ __device__ __forceinline__ void collide_post(const R (&p)[9], const Pre<R> &q, R
         D0 = r00;
         D1 = (s1z + s1p + s1m) + Fx;  // momentum gains F for any omega_1, omega_2
         D2 = K.a * (s0p - s0m) + Fy;
-        D3 = R(2) * K.s * r00 + rho * (ux2 + uy2) + K.om[3] * q.N3 + K.w[3] * del3 + K.sw[3] * phi3;
-        D4 = rho * (ux2 - uy2) + K.om[4] * q.N4 + K.w[4] * del4 + K.sw[4] * phi4;
-        D5 = rho * uxuy + K.om[5] * q.N5 + K.sw[5] * phi5;
-        const R e6 = rho * uy * sux2, e7 = rho * ux * suy2;
-        const R e8x = r00 * K.s2 + rho * (K.s * (ux2 + uy2) + ux2 * uy2);  // eq8 - rr s^2
+        D3 = R(2) * K.s * r00 + rho_times<DEV>(rr, r00, ux2 + uy2) + K.om[3] * q.N3 +
+             K.w[3] * del3 + K.sw[3] * phi3;
+        D4 = rho_times<DEV>(rr, r00, ux2 - uy2) + K.om[4] * q.N4 + K.w[4] * del4 + K.sw[4] * phi4;
+        D5 = rho_times<DEV>(rr, r00, uxuy) + K.om[5] * q.N5 + K.sw[5] * phi5;
+        const R e6 = rho_times<DEV>(rr, r00, uy * sux2), e7 = rho_times<DEV>(rr, r00, ux * suy2);
+        const R e8x = r00 * K.s2 + rho_times<DEV>(rr, r00, K.s * (ux2 + uy2) + ux2 * uy2);  // eq8 - rr s^2
         if (HU) {
             D6 = e6 + R(0.5) * phi6;
             D7 = e7 + R(0.5) * phi7;
