@@ -13,7 +13,8 @@ Prints ONE JSON line: MLUPS of the whole job, the roofline of the step kernel
 (algorithmic bytes per launch / mean launch time from HIP events on the
 library's stream), the HBM traffic measured by rocprofv3 counters (when
 profiles/ holds a measurement of the current kernel source) and the CPU
-oracle timed on a bounded sample on the host.
+oracle timed on a bounded sample on the host.  On the cavity it also times
+a cold start to a residual of 1e-8 (in FP64).
 """
 import argparse
 import hashlib
@@ -140,6 +141,33 @@ def cpu_baseline(name, collision, budget_s=10.0):
                        f"from the same start, {'RC' if collision == 0 else 'RNR'}")
 
 
+def time_to_steady(name, tol=1e-8, check_every=1000, cap=2_000_000):
+    """Cold start (fluid at rest) to a per-step residual <= tol, in FP64:
+    FP32 storage has a residual floor near 1e-7..1e-6 (rounding noise keeps
+    the weakly damped acoustic modes alive), so it never reaches 1e-8.
+    Returns steps and wall seconds (the residual is checked every
+    `check_every` steps, so steps are resolved to that)."""
+    import torch
+
+    from paper_2103_02119_amd import lbm as L
+
+    lat, _ = setup(name, L.LBM_FP64, L.LBM_RC)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, R = 0, float("inf")
+    while steps < cap:
+        lat.step(check_every)
+        steps += check_every
+        R = lat.residual()
+        if R <= tol:
+            break
+    wall = time.perf_counter() - t0
+    lat.close()
+    return dict(cold_steps=steps if R <= tol else None, cold_seconds=round(wall, 3),
+                residual=R, tol=tol, precision="fp64", collision="RC",
+                checked_every=check_every, warm_steps=None, warm_seconds=None)
+
+
 def copy_probe(nbytes=1 << 30, reps=20):
     """Plain device copy of a known size (counter calibration and the
     achievable HBM bandwidth)."""
@@ -174,6 +202,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-steady", action="store_true",
+                    help="skip the cold-start time-to-steady-state run (cavity only)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -274,6 +304,8 @@ def main():
         "mass": sums[0],
         "nonfinite_at_step": blew_up,
     }
+    if args.workload == "cavity" and not args.no_steady:
+        out["time_to_steady"] = time_to_steady(args.workload)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, L.LBM_RC, args.cpu_budget)
     print(json.dumps(out), flush=True)

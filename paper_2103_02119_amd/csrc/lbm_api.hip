@@ -67,7 +67,6 @@ static int fail_ctx(lbm_ctx *ctx, int code, const char *fmt, ...) {
                             "%s failed: %s", #call, hipGetErrorString(e_));            \
     } while (0)
 
-static int pitch_of(int nx) { return (nx + kWave - 1) / kWave * kWave; }
 
 static size_t value_bytes(int prec) { return f32_storage(prec) ? sizeof(float) : sizeof(double); }
 
@@ -104,10 +103,12 @@ static double feq_host(int k, double rho, double ux, double uy, double s, double
     return rho * px * py;
 }
 
+namespace lbm {
+
 template <typename R>
-static void fill_consts(const lbm_ctx *c, Consts<R> &K) {
-    const double a = c->a, s = c->opts.cs2;
-    const double *w = c->rates;
+void fill_consts(const CaseSpec &c, Consts<R> &K) {
+    const double a = c.a, s = c.cs2;
+    const double *w = c.rates;
     K.a = R(a);
     K.inv_a = R(1.0 / a);
     K.a2 = R(a * a);
@@ -115,11 +116,11 @@ static void fill_consts(const lbm_ctx *c, Consts<R> &K) {
     K.half_inv_a = R(0.5 / a);
     K.s = R(s);
     K.s2 = R(s * s);
-    K.rr = R(c->prec == kFP64 ? 0.0 : c->opts.rho0);
-    K.Fx = R(c->opts.force[0]);
-    K.Fy = R(c->opts.force[1]);
-    K.hFx = R(0.5 * c->opts.force[0]);
-    K.hFy = R(0.5 * c->opts.force[1]);
+    K.rr = R(c.prec == kFP64 ? 0.0 : c.rho0);
+    K.Fx = R(c.force[0]);
+    K.Fy = R(c.force[1]);
+    K.hFx = R(0.5 * c.force[0]);
+    K.hFy = R(0.5 * c.force[1]);
     for (int j = 0; j < 9; ++j) {
         K.w[j] = R(w[j]);
         K.om[j] = R(1.0 - w[j]);
@@ -137,40 +138,95 @@ static void fill_consts(const lbm_ctx *c, Consts<R> &K) {
     K.q1 = R(1.0 - 3.0 * s);
     K.q2 = R(a * a - 3.0 * s);
     for (int f = 0; f < 4; ++f) {
-        const bool mv = c->bc.type[f] == LBM_BC_MOVING_WALL;
-        const double ux = mv ? c->bc.u_wall[f][0] : 0.0, uy = mv ? c->bc.u_wall[f][1] : 0.0;
+        const bool mv = c.bc.type[f] == LBM_BC_MOVING_WALL;
+        const double ux = mv ? c.bc.u_wall[f][0] : 0.0, uy = mv ? c.bc.u_wall[f][1] : 0.0;
         for (int k = 0; k < 9; ++k)
-            K.dwall[f][k] = R(feq_host(opp_of(k), c->opts.rho0, ux, uy, s, a) -
-                              feq_host(k, c->opts.rho0, ux, uy, s, a));
+            K.dwall[f][k] = R(feq_host(opp_of(k), c.rho0, ux, uy, s, a) -
+                              feq_host(k, c.rho0, ux, uy, s, a));
     }
 }
+template void fill_consts<float>(const CaseSpec &, Consts<float> &);
+template void fill_consts<double>(const CaseSpec &, Consts<double> &);
+
+void fill_host_side(const CaseSpec &c, HostSide &H) {
+    for (int k = 0; k < 9; ++k) H.wrest[k] = feq_host(k, 1.0, 0.0, 0.0, c.cs2, c.a);
+    H.rho0 = c.rho0;
+    H.a = c.a;
+    H.s = c.cs2;
+    H.Fx = c.force[0];
+    H.Fy = c.force[1];
+    H.dev = c.prec == kFP64 ? 0 : 1;
+}
+
+void base_geometry(const CaseSpec &c, size_t f_bytes, Geometry &G) {
+    memset(&G, 0, sizeof(G));
+    G.nx = c.nx;
+    G.ny = c.ny;
+    G.pitch = pitch_of(c.nx);
+    G.plane = static_cast<long long>(G.pitch) * c.ny;
+    for (int f = 0; f < 4; ++f) G.bc[f] = c.bc.type[f];
+    G.corr = c.corr;
+    G.buf_ok = f_bytes < 0xffffffffULL ? 1 : 0;
+    G.nseg = (c.nx + kWave - 1) / kWave;
+}
+
+void set_rows(Geometry &G, int rows) {
+    if (rows > kMaxRows) rows = kMaxRows;
+    if (rows > G.ny) rows = G.ny;
+    if (rows < 1) rows = 1;
+    G.rows = rows;
+    G.nchunk = (G.ny + rows - 1) / rows;
+    G.ntile = G.nseg * G.nchunk;
+    G.nblocks = (G.ntile + kWavesPerBlock - 1) / kWavesPerBlock;
+    G.xcd_remap = (G.nblocks % 8 == 0) ? 1 : 0;
+}
+
+int pitch_of(int nx) { return (nx + kWave - 1) / kWave * kWave; }
+
+}  // namespace lbm
 
 // Launch shape and store policy, from measurements on MI355X: a wavefront
 // marches 2 rows on lattices below ~1M nodes (FP32) where latency dominates,
 // 4 below ~4M and 8 above; stores are non-temporal once the two population
 // buffers are well beyond the 256 MB Infinity Cache.
+void lbm::make_spec(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
+                    const lbm_opts *o, CaseSpec &spec) {
+    spec.nx = nx;
+    spec.ny = ny;
+    spec.a = r;
+    memcpy(spec.rates, rates, sizeof(spec.rates));
+    spec.bc = *bc;
+    spec.cs2 = o->cs2;
+    spec.force[0] = o->force[0];
+    spec.force[1] = o->force[1];
+    spec.rho0 = o->rho0;
+    spec.prec = o->precision;
+    spec.corr = o->corrections ? 1 : 0;
+}
+
+const char *lbm::create_error_text() { return g_create_error; }
+
+int lbm::set_create_error(const char *msg) {
+    snprintf(g_create_error, sizeof(g_create_error), "%s", msg);
+    return LBM_E_INVAL;
+}
+
+int lbm::auto_rows(long long nodes, int prec) {
+    if (nodes < (1LL << 20) && prec == kFP32Dev) return 2;
+    if (nodes < (1LL << 22)) return 4;
+    return 8;
+}
+
 static void choose_launch(lbm_ctx *c) {
     Geometry &G = c->G;
-    G.nseg = (c->nx + kWave - 1) / kWave;
     const long long nodes = static_cast<long long>(c->nx) * c->ny;
-    int rows = c->opts.rows_per_wave;
-    if (rows <= 0) {
-        if (nodes < (1LL << 20) && c->prec == kFP32Dev) rows = 2;
-        else if (nodes < (1LL << 22)) rows = 4;
-        else rows = 8;
-    }
-    if (rows > kMaxRows) rows = kMaxRows;
-    if (rows > c->ny) rows = c->ny;
-    G.rows = rows;
-    G.nchunk = (c->ny + rows - 1) / rows;
-    G.ntile = G.nseg * G.nchunk;
-    G.nblocks = (G.ntile + kWavesPerBlock - 1) / kWavesPerBlock;
-    G.xcd_remap = (G.nblocks % 8 == 0) ? 1 : 0;
+    const int rows = c->opts.rows_per_wave > 0 ? c->opts.rows_per_wave : auto_rows(nodes, c->prec);
+    set_rows(G, rows);
     G.nt_store = 2.0 * static_cast<double>(c->f_bytes) > 512.0 * 1024 * 1024 ? 1 : 0;
 }
 
-static int validate(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
-                    const lbm_opts *o) {
+int lbm::validate_case(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
+                       const lbm_opts *o) {
     if (nx < 3 || ny < 3) return fail_ctx(nullptr, LBM_E_INVAL, "nx and ny must be >= 3");
     if (!(r > 0.0) || !isfinite(r)) return fail_ctx(nullptr, LBM_E_INVAL, "r must be > 0");
     if (!rates) return fail_ctx(nullptr, LBM_E_INVAL, "rates is NULL");
@@ -233,7 +289,7 @@ extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const
     if (opts) o = *opts; else lbm_default_opts(&o);
     if (o.rho0 == 0.0) o.rho0 = 1.0;
     if (o.cs2 == 0.0) o.cs2 = fmin(1.0 / 3.0, 0.64 * r * r);
-    int rc = validate(nx, ny, r, rates, bc, &o);
+    int rc = validate_case(nx, ny, r, rates, bc, &o);
     if (rc != LBM_OK) return rc;
     size_t need = 0;
     rc = lbm_required_bytes(nx, ny, o.precision, &need);
@@ -259,26 +315,14 @@ extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const
     c->higher_unit = rates[6] == 1.0 && rates[7] == 1.0 && rates[8] == 1.0;
     snprintf(c->err, sizeof(c->err), "no error");
 
-    Geometry &G = c->G;
-    G.nx = nx;
-    G.ny = ny;
-    G.pitch = pitch_of(nx);
-    G.plane = static_cast<long long>(G.pitch) * ny;
-    for (int f = 0; f < 4; ++f) G.bc[f] = bc->type[f];
-    G.corr = o.corrections ? 1 : 0;
-    G.buf_ok = need < 0xffffffffULL ? 1 : 0;
+    CaseSpec spec;
+    make_spec(nx, ny, r, rates, bc, &o, spec);
     c->f_bytes = need;
+    base_geometry(spec, need, c->G);
     choose_launch(c);
-    fill_consts(c, c->Kd);
-    fill_consts(c, c->Kf);
-    for (int k = 0; k < 9; ++k) c->H.wrest[k] = feq_host(k, 1.0, 0.0, 0.0, o.cs2, r);
-    c->H.rho0 = o.rho0;
-    c->H.a = r;
-    c->H.s = o.cs2;
-    c->H.Fx = o.force[0];
-    c->H.Fy = o.force[1];
-    c->H.dev = c->prec == kFP64 ? 0 : 1;
-    c->f_bytes = need;
+    fill_consts(spec, c->Kd);
+    fill_consts(spec, c->Kf);
+    fill_host_side(spec, c->H);
 
     int status = LBM_OK;
     if (o.f_a) {

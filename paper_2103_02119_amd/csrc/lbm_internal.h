@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/lbm.h"
 
 namespace lbm {
 
@@ -73,6 +76,49 @@ struct HostSide {
     int dev;                 // 1: storage holds f - w rho0
 };
 
+// ---- batches of independent lattices (one launch advances all of them) ----
+// The two ping-pong buffers of a batch are two allocations with the same
+// layout; case c occupies values off .. off + 9 plane of each.
+struct BatchCase {
+    long long off;           // first value of the case in either buffer
+    int cur;                 // buffer (0 / 1) holding the current state
+    int pull;                // 1: the current buffer holds post-collision values (pull form)
+};
+// Work item of the batched step: a 64-column x rows tile of one case.
+struct BatchTile {
+    int c, seg, chunk, pad;
+};
+// Work item of the batched reductions: nodes [start, start + count) of case c,
+// whose current / previous buffers are in pull form when pc / pp is set.
+struct BatchRed {
+    int c, start, count, flags;  // flags: bit 0 pc, bit 1 pp
+};
+constexpr int kBatchRedNodes = 4096;  // nodes per reduction work item
+
+// ---- host helpers shared by the single-lattice and batch front ends ----
+// (implemented in lbm_api.hip; the lbm.h types are opaque here)
+struct CaseSpec {
+    int nx, ny;
+    double a;
+    double rates[9];
+    lbm_bc bc;
+    double cs2, force[2], rho0;
+    int prec, corr;
+};
+int validate_case(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
+                  const lbm_opts *o);  // fills the create error text on failure
+void make_spec(int nx, int ny, double r, const double *rates, const lbm_bc *bc, const lbm_opts *o,
+               CaseSpec &spec);
+template <typename R>
+void fill_consts(const CaseSpec &c, Consts<R> &K);
+void fill_host_side(const CaseSpec &c, HostSide &H);
+void base_geometry(const CaseSpec &c, size_t f_bytes, Geometry &G);
+void set_rows(Geometry &G, int rows);  // rows per wavefront and the tile counts that follow
+int auto_rows(long long nodes, int prec);
+int pitch_of(int nx);
+const char *create_error_text();
+int set_create_error(const char *msg);
+
 // ---- launchers implemented in lbm_kernels.hip (return hipError_t) ----
 hipError_t launch_step(int prec, int coll, bool pull, bool higher_unit, const void *src, void *dst,
                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
@@ -93,6 +139,22 @@ hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, d
                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
                        const HostSide &H, hipStream_t st);
 // out[0] = sum |u_cur - u_prev|^2, out[1] = sum |u_cur|^2, out[3] = NaN/Inf flag
+// batched step over the tile list (count in *ntiles, device memory) on a
+// persistent grid of `workgroups`; case c reads buf[cur ^ flip] and is in pull
+// form when force_pull or its own flag says so
+hipError_t launch_batch_step(int prec, int coll, bool higher_unit, void *buf0, void *buf1,
+                             const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                             const Geometry *geoms,
+                             const Consts<double> *Kd, const Consts<float> *Kf, int flip,
+                             int force_pull, int workgroups, hipStream_t st);
+// per-case residual sums of the batch: out[4 c + 0..3] as for launch_residual,
+// over the cases named by the reduction items (items of a case are contiguous)
+hipError_t launch_batch_residual(int prec, const void *buf0, const void *buf1,
+                                 const BatchRed *items, int nitems,
+                                 const BatchCase *cases, const Geometry *geoms,
+                                 const Consts<double> *Kd, const HostSide *H, double *partials,
+                                 const int *case_first, const int *case_count, int ncases,
+                                 double *out, hipStream_t st);
 hipError_t launch_residual(int prec, bool pull_cur, const void *cur, bool pull_prev,
                            const void *prev, double *partials, double *out, const Geometry &G,
                            const Consts<double> &Kd, const Consts<float> &Kf, const HostSide &H,

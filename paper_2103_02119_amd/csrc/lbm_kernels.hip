@@ -543,21 +543,11 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
     }
 }
 
+// One wavefront tile: 64 columns (segment seg) x G.rows rows (chunk).
 template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU>
-__global__ void __launch_bounds__(kBlock)
-step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, const Consts<R> K) {
-    const int lane = threadIdx.x & (kWave - 1);
-    int b = blockIdx.x;
-    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous run of tiles so neighbouring segments share its L2
-    if (G.xcd_remap) b = (b & 7) * (G.nblocks >> 3) + (b >> 3);
-    // the wavefront index is uniform across the wavefront; say so, so that all
-    // tile bookkeeping lives in scalar registers and branches are scalar
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    const int tile = b * kWavesPerBlock + wave;
-    if (tile >= G.ntile) return;
-    const int seg = tile % G.nseg;
-    const int chunk = tile / G.nseg;
+__device__ __forceinline__ void run_tile(const S *__restrict__ src, S *__restrict__ dst,
+                                         const Geometry &G, const Consts<R> &K, int lane, int seg,
+                                         int chunk) {
     const int x0 = seg * kWave;
     const int j0 = chunk * G.rows;
     const int j1 = min(j0 + G.rows, G.ny);
@@ -576,6 +566,93 @@ step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, co
     else
         march<S, R, DEV, COLL, PULL, HU, true>(src, dst, G, K, lane, j0, j1, x0, x, xraw, xlast,
                                                 active, wall_left, wall_right);
+}
+
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU>
+__global__ void __launch_bounds__(kBlock)
+step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, const Consts<R> K) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int b = blockIdx.x;
+    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous run of tiles so neighbouring segments share its L2
+    if (G.xcd_remap) b = (b & 7) * (G.nblocks >> 3) + (b >> 3);
+    // the wavefront index is uniform across the wavefront; say so, so that all
+    // tile bookkeeping lives in scalar registers and branches are scalar
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int tile = b * kWavesPerBlock + wave;
+    if (tile >= G.ntile) return;
+    run_tile<S, R, DEV, COLL, PULL, HU>(src, dst, G, K, lane, tile % G.nseg, tile / G.nseg);
+}
+
+// Batched step: a persistent grid walks the tile list of all active cases
+// (tiles of one case are contiguous).  The per-case geometry and constants
+// are read from device tables with a wavefront-uniform case index, so they
+// stay in scalar registers like kernel arguments.  The tile count lives in
+// device memory, so a captured graph stays valid when the list changes.
+template <typename S, typename R, bool DEV, int COLL, bool HU>
+__global__ void __launch_bounds__(kBlock)
+batch_step_kernel(S *__restrict__ buf0, S *__restrict__ buf1,
+                  const BatchTile *__restrict__ tiles, const int *__restrict__ ntiles,
+                  const BatchCase *__restrict__ cases, const Geometry *__restrict__ geoms,
+                  const Consts<R> *__restrict__ Ks, int flip, int force_pull) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nb = static_cast<int>(gridDim.x);
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int n = *ntiles;
+    for (int t = b * kWavesPerBlock + wave; t < n; t += nb * kWavesPerBlock) {
+        const BatchTile td = tiles[t];
+        const int c = __builtin_amdgcn_readfirstlane(td.c);
+        const int seg = __builtin_amdgcn_readfirstlane(td.seg);
+        const int chunk = __builtin_amdgcn_readfirstlane(td.chunk);
+        const Geometry &G = geoms[c];
+        const Consts<R> &K = Ks[c];
+        const int cur = __builtin_amdgcn_readfirstlane(cases[c].cur) ^ flip;
+        // derived from the kernel's buffer arguments, so that the compiler
+        // knows them to be global memory
+        const long long off = cases[c].off;
+        const S *src = (cur ? buf1 : buf0) + off;
+        S *dst = (cur ? buf0 : buf1) + off;
+        if (force_pull || cases[c].pull)
+            run_tile<S, R, DEV, COLL, true, HU>(src, dst, G, K, lane, seg, chunk);
+        else
+            run_tile<S, R, DEV, COLL, false, HU>(src, dst, G, K, lane, seg, chunk);
+    }
+}
+
+template <typename S, typename R, bool DEV>
+static hipError_t batch_dispatch(int coll, bool hu, void *b0, void *b1, const BatchTile *tiles,
+                                 const int *ntiles,
+                                 const BatchCase *cases, const Geometry *geoms,
+                                 const Consts<R> *K, int flip, int force_pull, int wgs,
+                                 hipStream_t st) {
+    const dim3 grid(wgs), block(kBlock);
+#define LBM_BSTEP(C, H)                                                                  \
+    hipLaunchKernelGGL((batch_step_kernel<S, R, DEV, C, H>), grid, block, 0, st,             \
+                       static_cast<S *>(b0), static_cast<S *>(b1), tiles, ntiles, cases, geoms, \
+                       K, flip, force_pull)
+    if (coll == kRC) {
+        if (hu) LBM_BSTEP(kRC, true); else LBM_BSTEP(kRC, false);
+    } else {
+        if (hu) LBM_BSTEP(kRNR, true); else LBM_BSTEP(kRNR, false);
+    }
+#undef LBM_BSTEP
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int prec, int coll, bool hu, void *b0, void *b1,
+                             const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                             const Geometry *geoms,
+                             const Consts<double> *Kd, const Consts<float> *Kf, int flip,
+                             int force_pull, int wgs, hipStream_t st) {
+    switch (prec) {
+    case kFP64: return batch_dispatch<double, double, false>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, force_pull, wgs, st);
+    case kFP32Dev: return batch_dispatch<float, float, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kf, flip, force_pull, wgs, st);
+    case kFP64Dev: return batch_dispatch<double, double, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, force_pull, wgs, st);
+    case kFP32DevF64: return batch_dispatch<float, double, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, force_pull, wgs, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename S, typename R, bool DEV>
@@ -791,6 +868,94 @@ finalize_kernel(const double *__restrict__ partials, int nparts, double *__restr
     }
     // flag: any non-zero survives the sum as non-zero
     block_sum4(acc, out);
+}
+
+// Batched residual: one workgroup per reduction item (a run of nodes of one
+// case), then one workgroup per case sums that case's item partials in a
+// fixed order, so every case's result is deterministic.
+template <typename S, bool PC, bool PP>
+__device__ __forceinline__ void batch_residual_item(const S *cur, const S *prev, const Geometry &G,
+                                                    const Consts<double> &K, const HostSide &H,
+                                                    int start, int count, double (&acc)[4]) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const int idx = start + i;
+        const int x = idx % G.nx, j = idx / G.nx;
+        const RowInfo ri = row_info(j, G);
+        const ColInfo ci = col_info(x, G);
+        double f9[9], r, vx, vy, r0, wx, wy;
+        load_node<S, double, PC>(cur, G, K, ri, ci, f9);
+        macro_of(f9, H, r, vx, vy);
+        load_node<S, double, PP>(prev, G, K, ri, ci, f9);
+        macro_of(f9, H, r0, wx, wy);
+        const double dx = vx - wx, dy = vy - wy;
+        acc[0] += dx * dx + dy * dy;
+        acc[1] += vx * vx + vy * vy;
+        if (!isfinite(vx) || !isfinite(vy) || !isfinite(wx) || !isfinite(wy)) acc[3] = 1.0;
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kReduceBlock)
+batch_residual_kernel(const S *__restrict__ buf0, const S *__restrict__ buf1,
+                      const BatchRed *__restrict__ items, const BatchCase *__restrict__ cases,
+                      const Geometry *__restrict__ geoms, const Consts<double> *__restrict__ Kd,
+                      const HostSide *__restrict__ Hs, double *__restrict__ partials) {
+    const BatchRed it = items[blockIdx.x];
+    const int c = it.c;
+    const Geometry &G = geoms[c];
+    const Consts<double> &K = Kd[c];
+    const HostSide &H = Hs[c];
+    const long long off = cases[c].off;
+    const S *cur = (cases[c].cur ? buf1 : buf0) + off;
+    const S *prev = (cases[c].cur ? buf0 : buf1) + off;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    switch (it.flags & 3) {
+    case 0: batch_residual_item<S, false, false>(cur, prev, G, K, H, it.start, it.count, acc); break;
+    case 1: batch_residual_item<S, true, false>(cur, prev, G, K, H, it.start, it.count, acc); break;
+    case 2: batch_residual_item<S, false, true>(cur, prev, G, K, H, it.start, it.count, acc); break;
+    default: batch_residual_item<S, true, true>(cur, prev, G, K, H, it.start, it.count, acc); break;
+    }
+    block_sum4(acc, partials + 4 * blockIdx.x);
+}
+
+// out[4 c ..] = fixed-order sum of the partials of items first[c] .. first[c] + count[c] - 1
+__global__ void __launch_bounds__(kReduceBlock)
+batch_finalize_kernel(const double *__restrict__ partials, const int *__restrict__ first,
+                      const int *__restrict__ count, double *__restrict__ out) {
+    const int c = blockIdx.x;
+    const int f = first[c], n = count[c];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double *p = partials + 4 * (f + i);
+        acc[0] += p[0];
+        acc[1] += p[1];
+        acc[2] += p[2];
+        acc[3] = fmax(acc[3], p[3]);
+    }
+    block_sum4(acc, out + 4 * c);
+}
+
+hipError_t launch_batch_residual(int prec, const void *b0, const void *b1,
+                                 const BatchRed *items, int nitems,
+                                 const BatchCase *cases, const Geometry *geoms,
+                                 const Consts<double> *Kd, const HostSide *H, double *partials,
+                                 const int *case_first, const int *case_count, int ncases,
+                                 double *out, hipStream_t st) {
+    if (nitems > 0) {
+        if (f32_storage(prec))
+            hipLaunchKernelGGL(batch_residual_kernel<float>, dim3(nitems), dim3(kReduceBlock), 0,
+                               st, static_cast<const float *>(b0), static_cast<const float *>(b1),
+                               items, cases, geoms, Kd, H, partials);
+        else
+            hipLaunchKernelGGL(batch_residual_kernel<double>, dim3(nitems), dim3(kReduceBlock), 0,
+                               st, static_cast<const double *>(b0), static_cast<const double *>(b1),
+                               items, cases, geoms, Kd, H, partials);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(ncases), dim3(kReduceBlock), 0, st, partials,
+                       case_first, case_count, out);
+    return hipGetLastError();
 }
 
 static int reduce_blocks(const Geometry &G) {

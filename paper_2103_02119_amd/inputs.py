@@ -90,3 +90,23 @@ def relative_noise(seed: int, nx: int, ny: int, amp: float = 1e-3):
 def cavity_rest(nx: int, ny: int, rho0: float = 1.0):
     """Fluid at rest (the cavity's cold start)."""
     return np.full((ny, nx), rho0), np.zeros((ny, nx)), np.zeros((ny, nx))
+
+
+def batch_sweep(n: int = 512, seed: int = DEFAULT_SEED, kinds=("cavity", "channel"),
+                nx_range=(64, 512), re_range=(100.0, 5000.0), ratios=(0.25, 0.5, 1.0),
+                speed: float = 0.05):
+    """Seeded parameters of n independent cases: kind drawn from `kinds`,
+    nx ~ U{nx_range}, r from `ratios`, ny = round(nx r) (at least 3),
+    Re ~ U(re_range), velocity scale `speed` (lid speed or centreline
+    velocity).  Plain parameters only; turning them into relaxation rates and
+    forces is the caller's business."""
+    g = rng(seed)
+    out = []
+    for _ in range(n):
+        kind = kinds[int(g.integers(len(kinds)))]
+        nx = int(g.integers(nx_range[0], nx_range[1] + 1))
+        r = float(ratios[int(g.integers(len(ratios)))])
+        ny = max(3, int(round(nx * r)))
+        re = float(g.uniform(*re_range))
+        out.append(dict(kind=kind, nx=nx, ny=ny, r=r, Re=re, U=speed))
+    return out

@@ -29,6 +29,11 @@ EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fiel
            "lbm_moments", "lbm_residual", "lbm_sums", "lbm_get_populations",
            "lbm_set_populations", "lbm_steps_done", "lbm_launch_shape", "lbm_last_error",
            "lbm_destroy")
+BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fields",
+                 "lbm_batch_set_active", "lbm_batch_step", "lbm_batch_residuals",
+                 "lbm_batch_run_to_steady", "lbm_batch_moments", "lbm_batch_get_populations",
+                 "lbm_batch_set_populations", "lbm_batch_steps_done", "lbm_batch_autotune",
+                 "lbm_batch_launch_shape", "lbm_batch_last_error", "lbm_batch_destroy")
 
 
 class LbmError(RuntimeError):
@@ -57,6 +62,31 @@ class lbm_opts(ctypes.Structure):
     ]
 
 
+class lbm_case(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int),
+        ("ny", ctypes.c_int),
+        ("r", ctypes.c_double),
+        ("rates", ctypes.c_double * 9),
+        ("bc", lbm_bc),
+        ("cs2", ctypes.c_double),
+        ("force", ctypes.c_double * 2),
+        ("rho0", ctypes.c_double),
+    ]
+
+
+class lbm_batch_opts(ctypes.Structure):
+    _fields_ = [
+        ("collision", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("corrections", ctypes.c_int),
+        ("rows_per_wave", ctypes.c_int),
+        ("workgroups", ctypes.c_int),
+        ("graph_steps", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 _CTX = ctypes.c_void_p
@@ -70,6 +100,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
+    # PyTorch-ROCm ships its own HIP and HSA runtimes.  Load them first, so
+    # that the library binds to the runtime already in the process: if the
+    # system runtime came first, torch's own would later fail to open the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     L.lbm_default_opts.argtypes = [ctypes.POINTER(lbm_opts)]
     L.lbm_default_opts.restype = None
@@ -95,6 +132,33 @@ def load():
     for name in ("lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step", "lbm_moments",
                  "lbm_residual", "lbm_sums", "lbm_get_populations", "lbm_set_populations",
                  "lbm_launch_shape", "lbm_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _I = ctypes.POINTER(ctypes.c_int)
+    _B = ctypes.c_void_p
+    L.lbm_batch_default_opts.argtypes = [ctypes.POINTER(lbm_batch_opts)]
+    L.lbm_batch_default_opts.restype = None
+    L.lbm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(lbm_case),
+                                   ctypes.POINTER(lbm_batch_opts), ctypes.POINTER(_B)]
+    L.lbm_batch_set_fields.argtypes = [_B, ctypes.c_int, _D, _D, _D]
+    L.lbm_batch_set_active.argtypes = [_B, _I]
+    L.lbm_batch_step.argtypes = [_B, ctypes.c_long]
+    L.lbm_batch_residuals.argtypes = [_B, _D]
+    L.lbm_batch_run_to_steady.argtypes = [_B, ctypes.c_double, ctypes.c_long, ctypes.c_long,
+                                          ctypes.POINTER(ctypes.c_long)]
+    L.lbm_batch_moments.argtypes = [_B, ctypes.c_int, _D, _D, _D]
+    L.lbm_batch_get_populations.argtypes = [_B, ctypes.c_int, _D]
+    L.lbm_batch_set_populations.argtypes = [_B, ctypes.c_int, _D]
+    L.lbm_batch_steps_done.argtypes = [_B, ctypes.c_int]
+    L.lbm_batch_steps_done.restype = ctypes.c_long
+    L.lbm_batch_autotune.argtypes = [_B, ctypes.c_int, _I, _I]
+    L.lbm_batch_launch_shape.argtypes = [_B, _I, _I, _I]
+    L.lbm_batch_last_error.argtypes = [_B]
+    L.lbm_batch_last_error.restype = ctypes.c_char_p
+    L.lbm_batch_destroy.argtypes = [_B]
+    for name in ("lbm_batch_create", "lbm_batch_set_fields", "lbm_batch_set_active",
+                 "lbm_batch_step", "lbm_batch_residuals", "lbm_batch_run_to_steady",
+                 "lbm_batch_moments", "lbm_batch_get_populations", "lbm_batch_set_populations",
+                 "lbm_batch_autotune", "lbm_batch_launch_shape", "lbm_batch_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -269,6 +333,173 @@ class Lattice:
         if getattr(self, "ctx", None):
             lbm_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ----------------------------------------------------------- batches (lbm_batch.h)
+
+def _bcheck(rc, b=None):
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_batch_last_error(b).decode(errors="replace"))
+
+
+def make_case(nx, ny, r, rates, bc_types=(LBM_BC_PERIODIC,) * 4, u_wall=((0.0, 0.0),) * 4,
+              cs2=0.0, force=(0.0, 0.0), rho0=1.0) -> lbm_case:
+    c = lbm_case()
+    c.nx, c.ny, c.r = int(nx), int(ny), float(r)
+    for j in range(9):
+        c.rates[j] = float(rates[j])
+    c.bc = make_bc(bc_types, u_wall)
+    c.cs2 = float(cs2)
+    c.force[0], c.force[1] = float(force[0]), float(force[1])
+    c.rho0 = float(rho0)
+    return c
+
+
+def lbm_batch_default_opts() -> lbm_batch_opts:
+    o = lbm_batch_opts()
+    load().lbm_batch_default_opts(ctypes.byref(o))
+    return o
+
+
+def lbm_batch_create(cases, opts: lbm_batch_opts | None = None):
+    arr = (lbm_case * len(cases))(*cases)
+    b = ctypes.c_void_p()
+    _bcheck(load().lbm_batch_create(len(cases), arr, ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(b)))
+    return b
+
+
+def lbm_batch_set_fields(b, c, nx, ny, rho=None, ux=None, uy=None):
+    keep = [_in(v, (ny, nx)) for v in (rho, ux, uy)]
+    _bcheck(load().lbm_batch_set_fields(b, int(c), *[k[1] for k in keep]), b)
+
+
+def lbm_batch_set_active(b, active):
+    a = (ctypes.c_int * len(active))(*[1 if x else 0 for x in active])
+    _bcheck(load().lbm_batch_set_active(b, a), b)
+
+
+def lbm_batch_step(b, n: int):
+    _bcheck(load().lbm_batch_step(b, int(n)), b)
+
+
+def lbm_batch_residuals(b, ncases):
+    R = np.empty(ncases)
+    _bcheck(load().lbm_batch_residuals(b, R.ctypes.data_as(_D)), b)
+    return R
+
+
+def lbm_batch_run_to_steady(b, ncases, tol, check_every, max_steps):
+    out = (ctypes.c_long * ncases)()
+    _bcheck(load().lbm_batch_run_to_steady(b, float(tol), int(check_every), int(max_steps), out), b)
+    return np.array(out[:], dtype=np.int64)
+
+
+def lbm_batch_moments(b, c, nx, ny):
+    rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
+    _bcheck(load().lbm_batch_moments(b, int(c), rho.ctypes.data_as(_D), ux.ctypes.data_as(_D),
+                                     uy.ctypes.data_as(_D)), b)
+    return rho, ux, uy
+
+
+def lbm_batch_get_populations(b, c, nx, ny):
+    f = np.empty((9, ny, nx))
+    _bcheck(load().lbm_batch_get_populations(b, int(c), f.ctypes.data_as(_D)), b)
+    return f
+
+
+def lbm_batch_set_populations(b, c, nx, ny, f):
+    a, p = _in(f, (9, ny, nx))
+    _bcheck(load().lbm_batch_set_populations(b, int(c), p), b)
+
+
+def lbm_batch_steps_done(b, c) -> int:
+    return load().lbm_batch_steps_done(b, int(c))
+
+
+def lbm_batch_autotune(b, trial_steps=5):
+    r, w = ctypes.c_int(), ctypes.c_int()
+    _bcheck(load().lbm_batch_autotune(b, int(trial_steps), ctypes.byref(r), ctypes.byref(w)), b)
+    return r.value, w.value
+
+
+def lbm_batch_launch_shape(b):
+    r, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _bcheck(load().lbm_batch_launch_shape(b, ctypes.byref(r), ctypes.byref(w), ctypes.byref(t)), b)
+    return r.value, w.value, t.value
+
+
+def lbm_batch_last_error(b=None) -> str:
+    return load().lbm_batch_last_error(b).decode(errors="replace")
+
+
+def lbm_batch_destroy(b):
+    if b:
+        load().lbm_batch_destroy(b)
+
+
+class Batch:
+    """Owns one lbm_batch: cases is a list of lbm_case (see make_case)."""
+
+    def __init__(self, cases, collision=LBM_RC, precision=LBM_FP64, corrections=True,
+                 rows_per_wave=0, workgroups=0, graph_steps=0):
+        self.shapes = [(c.nx, c.ny) for c in cases]
+        self.n = len(cases)
+        o = lbm_batch_default_opts()
+        o.collision, o.precision = int(collision), int(precision)
+        o.corrections = 1 if corrections else 0
+        o.rows_per_wave, o.workgroups, o.graph_steps = int(rows_per_wave), int(workgroups), int(graph_steps)
+        self.b = lbm_batch_create(cases, o)
+
+    def set_fields(self, c, rho=None, ux=None, uy=None):
+        lbm_batch_set_fields(self.b, c, *self.shapes[c], rho, ux, uy)
+
+    def set_active(self, active):
+        lbm_batch_set_active(self.b, active)
+
+    def step(self, n=1):
+        lbm_batch_step(self.b, n)
+
+    def residuals(self):
+        return lbm_batch_residuals(self.b, self.n)
+
+    def run_to_steady(self, tol, check_every, max_steps):
+        return lbm_batch_run_to_steady(self.b, self.n, tol, check_every, max_steps)
+
+    def moments(self, c):
+        return lbm_batch_moments(self.b, c, *self.shapes[c])
+
+    def get_populations(self, c):
+        return lbm_batch_get_populations(self.b, c, *self.shapes[c])
+
+    def set_populations(self, c, f):
+        lbm_batch_set_populations(self.b, c, *self.shapes[c], f)
+
+    def steps_done(self, c):
+        return lbm_batch_steps_done(self.b, c)
+
+    def autotune(self, trial_steps=5):
+        return lbm_batch_autotune(self.b, trial_steps)
+
+    def launch_shape(self):
+        return lbm_batch_launch_shape(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            lbm_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -1,6 +1,6 @@
-"""The C ABI library loads and exports every entry point include/lbm.h
-declares; host-side argument validation works without a GPU (no compute
-call is made here)."""
+"""The C ABI library loads and exports every entry point include/lbm.h and
+include/lbm_batch.h declare; host-side argument validation works without a
+GPU (no compute call is made here)."""
 import ctypes
 import os
 import re
@@ -11,10 +11,11 @@ from paper_2103_02119_amd import lbm as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
+BATCH_HEADER = os.path.join(ROOT, "include", "lbm_batch.h")
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
     return sorted(names)
@@ -30,13 +31,14 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(L.LIB_PATH)
-    for name in _declared_functions():
+    for name in _declared_functions() + _declared_functions(BATCH_HEADER):
         assert hasattr(lib, name), name
 
 
 def test_binding_uses_the_same_names():
     assert sorted(L.EXPORTS) == _declared_functions()
-    for name in L.EXPORTS:
+    assert sorted(L.BATCH_EXPORTS) == _declared_functions(BATCH_HEADER)
+    for name in L.EXPORTS + L.BATCH_EXPORTS:
         assert callable(getattr(L, name))
 
 
@@ -111,3 +113,60 @@ def test_default_opts():
     o = L.lbm_default_opts()
     assert o.rho0 == 1.0 and o.collision == L.LBM_RC and o.precision == L.LBM_FP64
     assert o.corrections == 1 and o.cs2 == 0.0 and o.stream is None
+
+
+# ---------------------------------------------------------------- batches
+
+def _case(**kw):
+    args = dict(nx=32, ny=16, r=0.5, rates=[1.0] * 9, bc_types=(0, 0, 1, 1), cs2=0.16)
+    args.update(kw)
+    return L.make_case(**args)
+
+
+@pytest.mark.parametrize("bad,fragment", [
+    (dict(nx=2), "case 1: nx and ny"),
+    (dict(r=0.0), "case 1: r must be"),
+    (dict(rates=[1.0] * 8 + [2.0]), "case 1: rates[8]"),
+    (dict(cs2=0.3), "case 1: cs2"),
+    (dict(bc_types=(0, 1, 1, 1)), "case 1: opposite faces"),
+])
+def test_batch_rejects_a_bad_case_with_its_index(bad, fragment):
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_batch_create([_case(), _case(**bad)])
+    assert e.value.code == L.LBM_E_INVAL
+    assert fragment in str(e.value)
+    assert fragment in L.lbm_batch_last_error(None)
+
+
+@pytest.mark.parametrize("field,value,fragment", [
+    ("collision", 2, "unknown collision"),
+    ("precision", 4, "unknown precision"),
+    ("rows_per_wave", 65, "rows_per_wave"),
+    ("workgroups", -1, "workgroups"),
+    ("graph_steps", 3, "graph_steps"),
+])
+def test_batch_rejects_bad_options(field, value, fragment):
+    o = L.lbm_batch_default_opts()
+    setattr(o, field, value)
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_batch_create([_case()], o)
+    assert e.value.code == L.LBM_E_INVAL and fragment in str(e.value)
+
+
+def test_batch_needs_a_case():
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_batch_create([])
+    assert e.value.code == L.LBM_E_INVAL
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU driver is present")
+def test_batch_without_gpu_fails_loudly():
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_batch_create([_case()])
+    assert e.value.code == L.LBM_E_DEVICE
+
+
+def test_batch_default_opts():
+    o = L.lbm_batch_default_opts()
+    assert o.collision == L.LBM_RC and o.precision == L.LBM_FP64 and o.corrections == 1
+    assert o.rows_per_wave == 0 and o.workgroups == 0 and o.graph_steps == 0 and o.stream is None
