@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -168,6 +170,80 @@ def time_to_steady(name, tol=1e-8, check_every=1000, cap=2_000_000):
                 checked_every=check_every, warm_steps=None, warm_seconds=None)
 
 
+def bench_sweep(args):
+    """The 512-case batch (cavities and channels, nx 64..512, r in
+    {0.25, 0.5, 1}, Re 100..5000, FP32 deviations) advanced together by the
+    persistent batched kernel, autotuned, graph-replayed."""
+    import torch
+
+    from paper_2103_02119_amd import inputs as I
+    from paper_2103_02119_amd import lbm as L
+    from paper_2103_02119_amd import workloads as W
+
+    prec = L.LBM_FP32_DEV if args.precision == "fp32dev" else L.LBM_FP64
+    bytes_per_lu = 72 if prec == L.LBM_FP32_DEV else 144
+    params = I.batch_sweep()
+    cases = W.sweep_cases(params)
+    nodes = sum(c.nx * c.ny for c in cases)
+    stream = torch.cuda.Stream()
+    b = L.Batch(cases, precision=prec, graph_steps=args.graph_steps, stream=stream.cuda_stream)
+    rows, wgs = b.autotune(5)
+    steps = (args.steps + args.graph_steps - 1) // args.graph_steps * args.graph_steps
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    R = b.residuals()
+    kern_ms = e0.elapsed_time(e1) / steps
+    achieved = bytes_per_lu * nodes / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS + % HBM roofline; time-to-steady-state warm-start vs cold",
+        "value": round(nodes * steps / wall / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == L.LBM_FP32_DEV else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch sweep {len(cases)} cases ({sum(p['kind'] == 'cavity' for p in params)} "
+                        f"cavities, the rest channels), nx 64..512, r in 0.25/0.5/1, Re 100..5000, "
+                        f"{nodes} nodes",
+            "collision": "RC",
+            "rows_per_wave": rows, "workgroups": wgs, "graph_steps": args.graph_steps,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_per_lu * nodes,
+            "kernel": "lbm::batch_step_kernel", "bytes_per_lu": bytes_per_lu,
+            "kernel_us": round(1e3 * kern_ms, 3),
+        },
+        "unstable_cases": int(np.isnan(R).sum()),
+    }
+    if args.steady_cap:
+        t0 = time.perf_counter()
+        got = b.run_to_steady(args.steady_tol, args.steady_every, args.steady_cap)
+        out["time_to_steady"] = {
+            "tol": args.steady_tol, "cap": args.steady_cap, "checked_every": args.steady_every,
+            "seconds": round(time.perf_counter() - t0, 3),
+            "converged": int((got > 0).sum()), "blew_up": int((got == -1).sum()),
+            "not_converged": int((got == -2).sum()),
+            "median_steps_converged": int(np.median(got[got > 0])) if (got > 0).any() else None,
+        }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_probe(nbytes=1 << 30, reps=20):
     """Plain device copy of a known size (counter calibration and the
     achievable HBM bandwidth)."""
@@ -193,7 +269,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cavity")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["sweep"], default="cavity")
+    ap.add_argument("--graph-steps", type=int, default=64, help="sweep: steps per captured graph")
+    ap.add_argument("--steady-cap", type=int, default=0,
+                    help="sweep: also run every case to --steady-tol, at most this many steps")
+    ap.add_argument("--steady-tol", type=float, default=1e-6)
+    ap.add_argument("--steady-every", type=int, default=1000)
     ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--chunk", type=int, default=10, help="launches per host call")
@@ -219,6 +300,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
     prec = L.LBM_FP32_DEV if args.precision == "fp32dev" else L.LBM_FP64
     bytes_per_lu = 72 if prec == L.LBM_FP32_DEV else 144

@@ -454,13 +454,16 @@ class Batch:
     """Owns one lbm_batch: cases is a list of lbm_case (see make_case)."""
 
     def __init__(self, cases, collision=LBM_RC, precision=LBM_FP64, corrections=True,
-                 rows_per_wave=0, workgroups=0, graph_steps=0):
+                 rows_per_wave=0, workgroups=0, graph_steps=0, stream=None):
+        """stream: a hipStream_t handle (e.g. torch.cuda.Stream().cuda_stream)
+        or None for a stream the batch creates."""
         self.shapes = [(c.nx, c.ny) for c in cases]
         self.n = len(cases)
         o = lbm_batch_default_opts()
         o.collision, o.precision = int(collision), int(precision)
         o.corrections = 1 if corrections else 0
         o.rows_per_wave, o.workgroups, o.graph_steps = int(rows_per_wave), int(workgroups), int(graph_steps)
+        o.stream = stream
         self.b = lbm_batch_create(cases, o)
 
     def set_fields(self, c, rho=None, ux=None, uy=None):
