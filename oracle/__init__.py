@@ -36,12 +36,22 @@ class Params(ctypes.Structure):
         ("corrections", ctypes.c_int),
         ("bc_type", ctypes.c_int * 4),
         ("u_wall", (ctypes.c_double * 2) * 4),
+        ("solid", ctypes.c_void_p),
     ]
 
 
 def make_params(nx, ny, a, cs2, omega, force=(0.0, 0.0), rho0=1.0, collision=RC,
-                corrections=True, bc=(PERIODIC,) * 4, u_wall=((0.0, 0.0),) * 4):
+                corrections=True, bc=(PERIODIC,) * 4, u_wall=((0.0, 0.0),) * 4, solid=None):
+    """solid: optional obstacle mask (ny, nx), nonzero = solid node."""
     p = Params()
+    if solid is not None:
+        m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
+        if m.shape != (int(ny), int(nx)):
+            raise ValueError(f"mask shape {m.shape} != {(int(ny), int(nx))}")
+        p._solid_keep = m  # the C side borrows this buffer
+        p.solid = m.ctypes.data
+    else:
+        p.solid = None
     p.nx, p.ny, p.a, p.cs2, p.rho0 = int(nx), int(ny), float(a), float(cs2), float(rho0)
     for k in range(9):
         p.omega[k] = float(omega[k])

@@ -299,6 +299,11 @@ void orc_collide_node(const orc_params *p, const double *f9, double drho_dx, dou
 #define IDX(p, j, i) ((size_t)(j) * (size_t)(p)->nx + (size_t)(i))
 #define FIDX(p, k, j, i) ((size_t)(k) * (size_t)(p)->nx * (size_t)(p)->ny + IDX(p, j, i))
 
+static int is_solid(const orc_params *p, int i, int j)
+{
+    return p->solid != NULL && p->solid[IDX(p, j, i)] != 0;
+}
+
 static void gather9(const orc_params *p, const double *f, int i, int j, double *f9)
 {
     for (int k = 0; k < 9; ++k)
@@ -313,7 +318,10 @@ void orc_init(const orc_params *p, const double *rho, const double *ux, const do
         for (int i = 0; i < p->nx; ++i) {
             double feq[9];
             const size_t n = IDX(p, j, i);
-            orc_feq(p, rho ? rho[n] : p->rho0, ux ? ux[n] : 0.0, uy ? uy[n] : 0.0, feq);
+            if (is_solid(p, i, j))
+                orc_feq(p, p->rho0, 0.0, 0.0, feq);
+            else
+                orc_feq(p, rho ? rho[n] : p->rho0, ux ? ux[n] : 0.0, uy ? uy[n] : 0.0, feq);
             for (int k = 0; k < 9; ++k)
                 f[FIDX(p, k, j, i)] = feq[k];
         }
@@ -331,22 +339,32 @@ void orc_density(const orc_params *p, const double *f, double *rho)
         }
 }
 
-/* Neighbour used by the density gradient: across a periodic face it wraps,
- * across a wall it is the node itself. */
-static int nb_x(const orc_params *p, int i, int d)
+/* Neighbour of node (i, j) used by the density gradient: across a periodic
+ * face it wraps, across a wall or onto a solid node it is the node itself. */
+static int nb_x(const orc_params *p, int i, int j, int d)
 {
-    const int n = i + d;
-    if (n < 0) return (p->bc_type[0] == ORC_PERIODIC) ? p->nx - 1 : i;
-    if (n >= p->nx) return (p->bc_type[1] == ORC_PERIODIC) ? 0 : i;
-    return n;
+    int n = i + d;
+    if (n < 0) {
+        if (p->bc_type[0] != ORC_PERIODIC) return i;
+        n = p->nx - 1;
+    } else if (n >= p->nx) {
+        if (p->bc_type[1] != ORC_PERIODIC) return i;
+        n = 0;
+    }
+    return is_solid(p, n, j) ? i : n;
 }
 
-static int nb_y(const orc_params *p, int j, int d)
+static int nb_y(const orc_params *p, int i, int j, int d)
 {
-    const int n = j + d;
-    if (n < 0) return (p->bc_type[2] == ORC_PERIODIC) ? p->ny - 1 : j;
-    if (n >= p->ny) return (p->bc_type[3] == ORC_PERIODIC) ? 0 : j;
-    return n;
+    int n = j + d;
+    if (n < 0) {
+        if (p->bc_type[2] != ORC_PERIODIC) return j;
+        n = p->ny - 1;
+    } else if (n >= p->ny) {
+        if (p->bc_type[3] != ORC_PERIODIC) return j;
+        n = 0;
+    }
+    return is_solid(p, i, n) ? j : n;
 }
 
 /* Central differences (the paper computes the density gradient "using a
@@ -357,9 +375,11 @@ void orc_density_gradient(const orc_params *p, const double *rho, double *gx, do
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            gx[IDX(p, j, i)] = (rho[IDX(p, j, nb_x(p, i, 1))] - rho[IDX(p, j, nb_x(p, i, -1))]) / 2.0;
+            gx[IDX(p, j, i)] =
+                (rho[IDX(p, j, nb_x(p, i, j, 1))] - rho[IDX(p, j, nb_x(p, i, j, -1))]) / 2.0;
             gy[IDX(p, j, i)] =
-                (rho[IDX(p, nb_y(p, j, 1), i)] - rho[IDX(p, nb_y(p, j, -1), i)]) / (2.0 * p->a);
+                (rho[IDX(p, nb_y(p, i, j, 1), i)] - rho[IDX(p, nb_y(p, i, j, -1), i)]) /
+                (2.0 * p->a);
         }
 }
 
@@ -392,8 +412,10 @@ void orc_collide(const orc_params *p, const double *f, double *ft)
 /* Source of the link k that arrives at node (i, j) under perfect-shift
  * streaming f_i(x, t+1) = f~_i(x - e_i, t).  Returns -1 and the (periodically
  * wrapped) source node, or the index of the wall face the link crosses
- * (half-way bounce-back).  A link crossing two wall faces takes the moving one
- * if exactly one of them moves, else the y face. */
+ * (half-way bounce-back), or ORC_OBSTACLE when the source is a solid node.
+ * A link crossing two wall faces takes the moving one if exactly one of them
+ * moves, else the y face; a link that leaves the domain never sees the mask. */
+#define ORC_OBSTACLE 4
 static int link_source(const orc_params *p, int i, int j, int k, int *si_out, int *sj_out)
 {
     const int nx = p->nx, ny = p->ny;
@@ -410,6 +432,7 @@ static int link_source(const orc_params *p, int i, int j, int k, int *si_out, in
     if (si >= nx) si -= nx;
     if (sj < 0) sj += ny;
     if (sj >= ny) sj -= ny;
+    if (is_solid(p, si, sj)) return ORC_OBSTACLE;
     *si_out = si;
     *sj_out = sj;
     return -1;
@@ -417,7 +440,7 @@ static int link_source(const orc_params *p, int i, int j, int k, int *si_out, in
 
 /* (feq_ibar - feq_i)(rho_w, u_w) of every face; rho_w = rho0, u_w = 0 for a
  * stationary wall (then the difference vanishes). */
-static void wall_terms(const orc_params *p, double dwall[4][9])
+static void wall_terms(const orc_params *p, double dwall[5][9])
 {
     for (int face = 0; face < 4; ++face) {
         double feq[9];
@@ -426,18 +449,25 @@ static void wall_terms(const orc_params *p, double dwall[4][9])
         for (int k = 0; k < 9; ++k)
             dwall[face][k] = feq[OPP[k]] - feq[k];
     }
+    for (int k = 0; k < 9; ++k)
+        dwall[ORC_OBSTACLE][k] = 0.0;  /* obstacles are at rest */
 }
 
 /* Streaming by perfect shift with periodic wrap or half-way bounce-back
  * (moving-wall form of Sec. 5.2) where the source node lies outside. */
 void orc_stream(const orc_params *p, const double *ft, double *f)
 {
-    double dwall[4][9];
+    double dwall[5][9], rest[9];
     wall_terms(p, dwall);
+    orc_feq(p, p->rho0, 0.0, 0.0, rest);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i)
             for (int k = 0; k < 9; ++k) {
+                if (is_solid(p, i, j)) {
+                    f[FIDX(p, k, j, i)] = rest[k];
+                    continue;
+                }
                 int si = 0, sj = 0;
                 const int face = link_source(p, i, j, k, &si, &sj);
                 if (face >= 0)
@@ -461,20 +491,24 @@ static double node_density(const orc_params *p, const double *f, int i, int j)
  * central-difference density gradient) and streamed as in orc_stream. */
 void orc_step_node(const orc_params *p, const double *f, int i, int j, double *out9)
 {
-    double T[81], Ti[81], dwall[4][9];
+    double T[81], Ti[81], dwall[5][9];
     orc_T(p->a, T);
     orc_Tinv(p->a, Ti);
     wall_terms(p, dwall);
+    if (is_solid(p, i, j)) {
+        orc_feq(p, p->rho0, 0.0, 0.0, out9);
+        return;
+    }
     for (int k = 0; k < 9; ++k) {
         int si = i, sj = j;
         const int face = link_source(p, i, j, k, &si, &sj);
         const int comp = face >= 0 ? OPP[k] : k;
         double f9[9], o9[9];
         gather9(p, f, si, sj, f9);
-        const double gx = (node_density(p, f, nb_x(p, si, 1), sj) -
-                           node_density(p, f, nb_x(p, si, -1), sj)) / 2.0;
-        const double gy = (node_density(p, f, si, nb_y(p, sj, 1)) -
-                           node_density(p, f, si, nb_y(p, sj, -1))) / (2.0 * p->a);
+        const double gx = (node_density(p, f, nb_x(p, si, sj, 1), sj) -
+                           node_density(p, f, nb_x(p, si, sj, -1), sj)) / 2.0;
+        const double gy = (node_density(p, f, si, nb_y(p, si, sj, 1)) -
+                           node_density(p, f, si, nb_y(p, si, sj, -1))) / (2.0 * p->a);
         collide_with(p, T, Ti, f9, gx, gy, o9);
         out9[k] = o9[comp] - (face >= 0 ? dwall[face][k] : 0.0);
     }

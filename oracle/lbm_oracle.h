@@ -41,6 +41,12 @@ typedef struct {
     int corrections;   /* 1: add Eq. 23-26 corrections; 0: leave them out */
     int bc_type[4];    /* per face, ORC_PERIODIC / ORC_WALL / ORC_MOVING_WALL */
     double u_wall[4][2];
+    /* optional obstacle mask [ny][nx], nonzero = solid node (NULL: none).
+     * A link whose source node is solid bounces back half-way at rest
+     * (Sec. 5.2 with u_w = 0); a solid neighbour's density is replaced by the
+     * node's own in the density gradient (as at a wall); solid nodes hold the
+     * rest state feq(rho0, 0). */
+    const unsigned char *solid;
 } orc_params;
 
 /* --- matrices (row-major 9x9) --- */
