@@ -135,13 +135,13 @@ int lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
 
 /* Steady-state residual of the last step,
  * R = sqrt(sum |u^n - u^{n-1}|^2) / sqrt(sum |u^n|^2), summed in FP64 over all
- * nodes with a deterministic two-pass reduction.  Synchronizes.
+ * fluid nodes with a deterministic two-pass reduction.  Synchronizes.
  * Errors: LBM_E_STATE before the first step (or after set_fields /
  * set_populations); LBM_E_UNSTABLE if any velocity is NaN or Inf (*R is then
  * NaN); LBM_E_DEVICE. */
 int lbm_residual(lbm_ctx *ctx, double *R);
 
-/* FP64 totals over all nodes at the current time level: out[0] = sum rho,
+/* FP64 totals over all fluid nodes at the current time level: out[0] = sum rho,
  * out[1] = sum rho ux, out[2] = sum rho uy (momentum including the F/2
  * shift).  Deterministic.  Synchronizes.  Errors: LBM_E_UNSTABLE (NaN/Inf),
  * LBM_E_DEVICE. */
@@ -153,6 +153,17 @@ int lbm_sums(lbm_ctx *ctx, double out[3]);
  * Errors: LBM_E_DEVICE, LBM_E_NOMEM (staging buffer). */
 int lbm_get_populations(lbm_ctx *ctx, double *f);
 int lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/* Obstacle mask: host unsigned char[ny][nx], nonzero = solid node; NULL
+ * removes it.  A link whose source node is solid bounces back half-way with
+ * the wall at rest (Sec. 5.2, Eq. 57-59 with u_w = 0); a link that leaves the
+ * domain is handled by the face boundaries, never by the mask.  In the
+ * density gradient a solid neighbour's density is replaced by the node's own,
+ * as at a wall.  Solid nodes hold (and report) the rest state
+ * feq(rho0, 0) and are left out of lbm_sums and lbm_residual.  The mask is
+ * copied; it takes effect for every later call.  Synchronizes.
+ * Errors: LBM_E_NOMEM, LBM_E_DEVICE. */
+int lbm_set_mask(lbm_ctx *ctx, const unsigned char *mask);
 
 /* Number of steps taken since creation (set_fields / set_populations do not
  * reset it). */

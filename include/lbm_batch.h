@@ -69,6 +69,11 @@ int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_batch_opts *op
 int lbm_batch_set_fields(lbm_batch *b, int c, const double *rho, const double *ux,
                          const double *uy);
 
+/* Obstacle mask of case c (as lbm_set_mask): host unsigned char[ny][nx],
+ * nonzero = solid; NULL removes it.  Synchronizes.
+ * Errors: LBM_E_INVAL (bad c), LBM_E_NOMEM, LBM_E_DEVICE. */
+int lbm_batch_set_mask(lbm_batch *b, int c, const unsigned char *mask);
+
 /* Marks which cases advance (active[c] != 0).  Inactive cases keep their state
  * and step count.  Takes effect for the next lbm_batch_step.
  * Errors: LBM_E_INVAL. */

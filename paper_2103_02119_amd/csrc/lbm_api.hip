@@ -46,6 +46,8 @@ struct lbm_ctx {
     double *d_partials;  // reduction partials + results
     double *d_stage;     // FP64 staging for host transfers (lazy)
     size_t stage_bytes;
+    unsigned char *d_mask;        // obstacle mask [ny][pitch] (or null)
+    unsigned char *d_tile_solid;  // per step tile: obstacle in its neighbourhood
     long steps;
     char err[512];
 };
@@ -137,6 +139,8 @@ void fill_consts(const CaseSpec &c, Consts<R> &K) {
     K.e2 = R((3.0 * s - a * a) / 2.0);
     K.q1 = R(1.0 - 3.0 * s);
     K.q2 = R(a * a - 3.0 * s);
+    for (int k = 0; k < 9; ++k)
+        K.rest[k] = R(c.prec == kFP64 ? c.rho0 * feq_host(k, 1.0, 0.0, 0.0, s, a) : 0.0);
     for (int f = 0; f < 4; ++f) {
         const bool mv = c.bc.type[f] == LBM_BC_MOVING_WALL;
         const double ux = mv ? c.bc.u_wall[f][0] : 0.0, uy = mv ? c.bc.u_wall[f][1] : 0.0;
@@ -182,6 +186,30 @@ void set_rows(Geometry &G, int rows) {
 }
 
 int pitch_of(int nx) { return (nx + kWave - 1) / kWave * kWave; }
+
+int tile_has_solid(const Geometry &G, const unsigned char *m, int seg, int chunk) {
+    if (!m) return 0;
+    const int x0 = seg * kWave, j0 = chunk * G.rows;
+    const int j1 = j0 + G.rows < G.ny ? j0 + G.rows : G.ny;
+    // the tile pulls rows j0 - 1 .. j1 and columns x0 - 1 .. x0 + 64; the
+    // densities of its ring rows and halo columns pull one node further out
+    for (int jj = j0 - 2; jj <= j1 + 1; ++jj) {
+        int j = jj;
+        if (j < 0 || j >= G.ny) {
+            if (G.bc[j < 0 ? kYmin : kYmax] != kPeriodic) continue;
+            j = (j + G.ny) % G.ny;
+        }
+        for (int xx = x0 - 2; xx <= x0 + kWave + 1; ++xx) {
+            int x = xx;
+            if (x < 0 || x >= G.nx) {
+                if (G.bc[x < 0 ? kXmin : kXmax] != kPeriodic) continue;
+                x = (x + G.nx) % G.nx;
+            }
+            if (m[static_cast<size_t>(j) * G.nx + x]) return 1;
+        }
+    }
+    return 0;
+}
 
 }  // namespace lbm
 
@@ -487,6 +515,45 @@ extern "C" int lbm_set_populations(lbm_ctx *c, const double *f) {
     return LBM_OK;
 }
 
+extern "C" int lbm_set_mask(lbm_ctx *c, const unsigned char *mask) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (!mask) {
+        if (c->d_mask) HIP_OR_FAIL(c, hipFree(c->d_mask));
+        if (c->d_tile_solid) HIP_OR_FAIL(c, hipFree(c->d_tile_solid));
+        c->d_mask = nullptr;
+        c->d_tile_solid = nullptr;
+        c->G.mask = nullptr;
+        c->G.tile_solid = nullptr;
+        return LBM_OK;
+    }
+    const Geometry &G = c->G;
+    const size_t mbytes = static_cast<size_t>(G.pitch) * G.ny;
+    if (!c->d_mask) HIP_OR_FAIL(c, hipMalloc(&c->d_mask, mbytes));
+    if (!c->d_tile_solid) HIP_OR_FAIL(c, hipMalloc(&c->d_tile_solid, G.ntile));
+    unsigned char *pitched = static_cast<unsigned char *>(calloc(mbytes, 1));
+    unsigned char *flags = static_cast<unsigned char *>(calloc(G.ntile, 1));
+    if (!pitched || !flags) {
+        free(pitched);
+        free(flags);
+        return fail_ctx(c, LBM_E_NOMEM, "out of host memory");
+    }
+    for (int j = 0; j < G.ny; ++j)
+        for (int i = 0; i < G.nx; ++i)
+            pitched[static_cast<size_t>(j) * G.pitch + i] = mask[static_cast<size_t>(j) * G.nx + i] ? 1 : 0;
+    for (int t = 0; t < G.ntile; ++t)
+        flags[t] = static_cast<unsigned char>(tile_has_solid(G, mask, t % G.nseg, t / G.nseg));
+    hipError_t e1 = hipMemcpy(c->d_mask, pitched, mbytes, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(c->d_tile_solid, flags, G.ntile, hipMemcpyHostToDevice);
+    free(pitched);
+    free(flags);
+    HIP_OR_FAIL(c, e1);
+    HIP_OR_FAIL(c, e2);
+    c->G.mask = c->d_mask;
+    c->G.tile_solid = c->d_tile_solid;
+    return LBM_OK;
+}
+
 extern "C" long lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : 0; }
 
 extern "C" int lbm_launch_shape(const lbm_ctx *c, int *rows_per_wave, int *workgroups) {
@@ -505,6 +572,8 @@ extern "C" int lbm_destroy(lbm_ctx *c) {
         if (c->owns[i] && c->f[i]) (void)hipFree(c->f[i]);
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_stage) (void)hipFree(c->d_stage);
+    if (c->d_mask) (void)hipFree(c->d_mask);
+    if (c->d_tile_solid) (void)hipFree(c->d_tile_solid);
     delete c;
     return LBM_OK;
 }

@@ -41,6 +41,8 @@ struct lbm_batch {
     std::vector<int> form_prev; // Form of each case's other buffer
     std::vector<int> active;
     std::vector<long> steps;
+    std::vector<std::vector<unsigned char>> hmask;  // host obstacle masks [ny][nx] (empty: none)
+    std::vector<unsigned char *> d_mask;            // device copies [ny][pitch]
     size_t vbytes;              // bytes per stored value
     size_t total_values;        // values per ping-pong buffer
     void *buf[2];
@@ -111,8 +113,10 @@ static int upload_tiles(lbm_batch *b) {
     for (int c = 0; c < b->n; ++c) {
         if (!b->active[c]) continue;
         const Geometry &G = b->G[c];
+        const unsigned char *m = b->hmask[c].empty() ? nullptr : b->hmask[c].data();
         for (int ch = 0; ch < G.nchunk; ++ch)
-            for (int s = 0; s < G.nseg; ++s) t.push_back(BatchTile{c, s, ch, 0});
+            for (int s = 0; s < G.nseg; ++s)
+                t.push_back(BatchTile{c, s, ch, tile_has_solid(G, m, s, ch)});
     }
     b->ntiles = static_cast<int>(t.size());
     if (b->ntiles > b->tile_cap) return fail(b, LBM_E_DEVICE, "tile list overflow");
@@ -211,6 +215,8 @@ extern "C" int lbm_batch_destroy(lbm_batch *b) {
                     b->d_partials, b->d_out, b->d_stage};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (unsigned char *p : b->d_mask)
+        if (p) (void)hipFree(p);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return LBM_OK;
@@ -252,6 +258,8 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
         b->form_prev.assign(ncases, kEmpty);
         b->active.assign(ncases, 1);
         b->steps.assign(ncases, 0);
+        b->hmask.resize(ncases);
+        b->d_mask.assign(ncases, nullptr);
     } catch (...) {
         delete b;
         return fail(nullptr, LBM_E_NOMEM, "out of host memory");
@@ -456,6 +464,37 @@ extern "C" int lbm_batch_moments(lbm_batch *b, int c, double *rho, double *ux, d
                                      b->stream));
     HIP_OK(b, hipStreamSynchronize(b->stream));
     return LBM_OK;
+}
+
+extern "C" int lbm_batch_set_mask(lbm_batch *b, int c, const unsigned char *mask) {
+    int rc = check_case(b, c);
+    if (rc != LBM_OK) return rc;
+    HIP_OK(b, hipStreamSynchronize(b->stream));
+    Geometry &G = b->G[c];
+    if (!mask) {
+        if (b->d_mask[c]) HIP_OK(b, hipFree(b->d_mask[c]));
+        b->d_mask[c] = nullptr;
+        b->hmask[c].clear();
+        G.mask = nullptr;
+    } else {
+        const size_t n = static_cast<size_t>(G.nx) * G.ny, mbytes = static_cast<size_t>(G.pitch) * G.ny;
+        std::vector<unsigned char> pitched;
+        try {
+            b->hmask[c].assign(mask, mask + n);
+            pitched.assign(mbytes, 0);
+        } catch (...) {
+            return fail(b, LBM_E_NOMEM, "out of host memory");
+        }
+        for (int j = 0; j < G.ny; ++j)
+            for (int i = 0; i < G.nx; ++i)
+                pitched[static_cast<size_t>(j) * G.pitch + i] = mask[static_cast<size_t>(j) * G.nx + i] ? 1 : 0;
+        if (!b->d_mask[c]) HIP_OK(b, hipMalloc(&b->d_mask[c], mbytes));
+        HIP_OK(b, hipMemcpy(b->d_mask[c], pitched.data(), mbytes, hipMemcpyHostToDevice));
+        G.mask = b->d_mask[c];
+    }
+    HIP_OK(b, hipMemcpyAsync(b->d_geoms + c, &G, sizeof(Geometry), hipMemcpyHostToDevice,
+                             b->stream));
+    return upload_tiles(b);
 }
 
 extern "C" int lbm_batch_set_active(lbm_batch *b, const int *active) {

@@ -50,6 +50,8 @@ struct Geometry {
     int buf_ok;              // 1: a population buffer is below 4 GiB (buffer addressing)
     int nt_store;            // 1: non-temporal population stores (buffers exceed the MALL)
     long long plane;         // pitch * ny
+    const unsigned char *mask;        // obstacle mask [ny][pitch], nonzero = solid (or null)
+    const unsigned char *tile_solid;  // per step-kernel tile: a solid node in its neighbourhood
 };
 
 // Model constants in the arithmetic type R of a kernel.
@@ -67,6 +69,7 @@ struct Consts {
     R e1, e2;                // (3 cs2 - 1)/2, (3 cs2 - a^2)/2 (B3/ux, B4/uy of Eq. 40)
     R q1, q2;                // 1 - 3 cs2, a^2 - 3 cs2 (Eq. 23-24)
     R dwall[4][9];           // (feq_opp(k) - feq_k)(rho0, u_wall[face]) per face
+    R rest[9];               // stored value of the rest state (solid nodes): rho0 w_k, or 0 as a deviation
 };
 
 // Per-context constants for the conversion kernels (always FP64).
@@ -114,6 +117,11 @@ void fill_consts(const CaseSpec &c, Consts<R> &K);
 void fill_host_side(const CaseSpec &c, HostSide &H);
 void base_geometry(const CaseSpec &c, size_t f_bytes, Geometry &G);
 void set_rows(Geometry &G, int rows);  // rows per wavefront and the tile counts that follow
+// 1 if a solid node lies within two nodes of step tile (seg, chunk): rows
+// j0 - 2 .. j1 + 1, columns x0 - 2 .. x0 + 65 (wrapped where periodic) -- the
+// tile pulls from one node around it, and the ring / halo densities it forms
+// pull from one node further out
+int tile_has_solid(const Geometry &G, const unsigned char *host_mask, int seg, int chunk);
 int auto_rows(long long nodes, int prec);
 int pitch_of(int nx);
 const char *create_error_text();

@@ -79,14 +79,21 @@ __device__ __forceinline__ ColInfo col_info(int x, const Geometry &G) {
 
 // Pre-collision populations of node (x, j): pulled with periodic wrap and
 // half-way bounce-back, f_k = f~_opp(k)(x) - (feq_opp(k) - feq_k)(rho0, u_w),
-// where the source node lies beyond a wall (Sec. 5.2).  Without PULL the
-// buffer already holds pre-collision values and is read in place.
+// where the source node lies beyond a wall (Sec. 5.2), or f_k = f~_opp(k)(x)
+// where it is a solid node of the obstacle mask (a wall at rest).  Without
+// PULL the buffer already holds pre-collision values and is read in place.
+// A solid node itself reads as the rest state.
 template <typename S, typename R, bool PULL>
 __device__ __forceinline__ void load_node(const S *__restrict__ src, const Geometry &G,
                                           const Consts<R> &K, const RowInfo &r,
                                           const ColInfo &c, R (&f)[9]) {
     const long long P = G.plane;
     const long long own = static_cast<long long>(r.j) * G.pitch + c.x;
+    if (G.mask && G.mask[own]) {  // a solid node holds the rest state
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = K.rest[k];
+        return;
+    }
     if (!PULL) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) f[k] = static_cast<R>(src[k * P + own]);
@@ -107,7 +114,11 @@ __device__ __forceinline__ void load_node(const S *__restrict__ src, const Geome
             const R d = use_x ? K.dwall[xf][k] : K.dwall[yf][k];
             f[k] = static_cast<R>(src[opp_of(k) * P + own]) - d;
         } else {
-            f[k] = static_cast<R>(src[k * P + static_cast<long long>(row) * G.pitch + col]);
+            const long long so = static_cast<long long>(row) * G.pitch + col;
+            if (G.mask && G.mask[so])  // solid source: half-way bounce-back at rest
+                f[k] = static_cast<R>(src[opp_of(k) * P + own]);
+            else
+                f[k] = static_cast<R>(src[k * P + so]);
         }
     }
 }
@@ -518,11 +529,31 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
         const R hrj = readlane(hr, j - j0);
         if (lane == 0) rl = wall_left ? rc : hlj;
         if (xraw == xlast) rgt = wall_right ? rc : hrj;
+        R rnu = rn, rbu = rb;
+        bool solid = false;
+        if (GENERIC && G.mask) {
+            // a solid neighbour's density is replaced by the node's own (as at a wall)
+            const unsigned char *m = G.mask;
+            const long long ro = static_cast<long long>(j) * G.pitch;
+            const int jn = row_of(j + 1);
+            const int jb = j > 0 ? j - 1 : (G.bc[kYmin] == kPeriodic ? G.ny - 1 : -1);
+            const int xl = x > 0 ? x - 1 : (G.bc[kXmin] == kPeriodic ? G.nx - 1 : -1);
+            const int xr = x < G.nx - 1 ? x + 1 : (G.bc[kXmax] == kPeriodic ? 0 : -1);
+            solid = m[ro + x] != 0;
+            if (xl >= 0 && m[ro + xl]) rl = rc;
+            if (xr >= 0 && m[ro + xr]) rgt = rc;
+            if (jn >= 0 && m[static_cast<long long>(jn) * G.pitch + x]) rnu = rc;
+            if (jb >= 0 && m[static_cast<long long>(jb) * G.pitch + x]) rbu = rc;
+        }
         const R gx = (rgt - rl) * R(0.5);
-        const R gy = (rn - rb) * K.half_inv_a;
+        const R gy = (rnu - rbu) * K.half_inv_a;
 
         R out[9];
         collide_post<R, DEV, COLL, HU>(cur, q, gx, gy, G.corr, K, out);
+        if (GENERIC && solid) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) out[k] = K.rest[k];
+        }
         if (active) store_node(dst, G, j, xraw, out);
         rb = rc;
         rc = rn;
@@ -547,7 +578,7 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
 template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU>
 __device__ __forceinline__ void run_tile(const S *__restrict__ src, S *__restrict__ dst,
                                          const Geometry &G, const Consts<R> &K, int lane, int seg,
-                                         int chunk) {
+                                         int chunk, bool near_solid) {
     const int x0 = seg * kWave;
     const int j0 = chunk * G.rows;
     const int j1 = min(j0 + G.rows, G.ny);
@@ -557,9 +588,10 @@ __device__ __forceinline__ void run_tile(const S *__restrict__ src, S *__restric
     const int x = min(xraw, G.nx - 1);
     const bool wall_left = (x0 == 0) && G.bc[kXmin] != kPeriodic;
     const bool wall_right = (xlast == G.nx - 1) && G.bc[kXmax] != kPeriodic;
-    // every pulled node (rows j0-1 .. j1, columns x0-1 .. x0+64) interior?
-    const bool interior =
-        G.buf_ok && (x0 > 0) && (x0 + kWave < G.nx) && (j0 >= 2) && (j1 <= G.ny - 2);
+    // every pulled node (rows j0-1 .. j1, columns x0-1 .. x0+64) interior
+    // and fluid?
+    const bool interior = G.buf_ok && !near_solid && (x0 > 0) && (x0 + kWave < G.nx) &&
+                          (j0 >= 2) && (j1 <= G.ny - 2);
     if (interior)
         march<S, R, DEV, COLL, PULL, HU, false>(src, dst, G, K, lane, j0, j1, x0, x, xraw, xlast,
                                                  active, wall_left, wall_right);
@@ -581,7 +613,9 @@ step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G, co
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int tile = b * kWavesPerBlock + wave;
     if (tile >= G.ntile) return;
-    run_tile<S, R, DEV, COLL, PULL, HU>(src, dst, G, K, lane, tile % G.nseg, tile / G.nseg);
+    const bool near_solid = G.tile_solid && G.tile_solid[tile];
+    run_tile<S, R, DEV, COLL, PULL, HU>(src, dst, G, K, lane, tile % G.nseg, tile / G.nseg,
+                                        near_solid);
 }
 
 // Batched step: a persistent grid walks the tile list of all active cases
@@ -606,6 +640,7 @@ batch_step_kernel(S *__restrict__ buf0, S *__restrict__ buf1,
         const int c = __builtin_amdgcn_readfirstlane(td.c);
         const int seg = __builtin_amdgcn_readfirstlane(td.seg);
         const int chunk = __builtin_amdgcn_readfirstlane(td.chunk);
+        const bool near_solid = __builtin_amdgcn_readfirstlane(td.pad) != 0;
         const Geometry &G = geoms[c];
         const Consts<R> &K = Ks[c];
         const int cur = __builtin_amdgcn_readfirstlane(cases[c].cur) ^ flip;
@@ -615,9 +650,9 @@ batch_step_kernel(S *__restrict__ buf0, S *__restrict__ buf1,
         const S *src = (cur ? buf1 : buf0) + off;
         S *dst = (cur ? buf0 : buf1) + off;
         if (force_pull || cases[c].pull)
-            run_tile<S, R, DEV, COLL, true, HU>(src, dst, G, K, lane, seg, chunk);
+            run_tile<S, R, DEV, COLL, true, HU>(src, dst, G, K, lane, seg, chunk, near_solid);
         else
-            run_tile<S, R, DEV, COLL, false, HU>(src, dst, G, K, lane, seg, chunk);
+            run_tile<S, R, DEV, COLL, false, HU>(src, dst, G, K, lane, seg, chunk, near_solid);
     }
 }
 
@@ -714,9 +749,10 @@ __global__ void init_feq_kernel(S *__restrict__ dst, const double *__restrict__ 
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
         const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
-        const double r = rho ? rho[idx] : H.rho0;
-        const double vx = ux ? ux[idx] : 0.0, vy = uy ? uy[idx] : 0.0;
         const long long o = static_cast<long long>(j) * G.pitch + x;
+        const bool solid = G.mask && G.mask[o];  // solid nodes take the rest state
+        const double r = (rho && !solid) ? rho[idx] : H.rho0;
+        const double vx = (ux && !solid) ? ux[idx] : 0.0, vy = (uy && !solid) ? uy[idx] : 0.0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             double f = r * px_of(cx_of(k), H.s, vx) * py_of(cy_of(k), H.s, H.a, vy);
@@ -734,9 +770,10 @@ __global__ void set_pop_kernel(S *__restrict__ dst, const double *__restrict__ f
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
         const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
         const long long o = static_cast<long long>(j) * G.pitch + x;
+        const bool solid = G.mask && G.mask[o];  // solid nodes take the rest state
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double v = f[k * n + idx];
+            double v = solid ? H.rho0 * H.wrest[k] : f[k * n + idx];
             if (H.dev) v -= H.rho0 * H.wrest[k];
             dst[k * G.plane + o] = static_cast<S>(v);
         }
@@ -820,6 +857,7 @@ sums_kernel(const S *__restrict__ src, double *__restrict__ partials, const Geom
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
         const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) continue;  // fluid only
         double f9[9], r, vx, vy;
         load_node<S, double, PULL>(src, G, K, row_info(j, G), col_info(x, G), f9);
         macro_of(f9, H, r, vx, vy);
@@ -841,6 +879,7 @@ residual_kernel(const SC *__restrict__ cur, const SP *__restrict__ prev,
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
         const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) continue;  // fluid only
         const RowInfo ri = row_info(j, G);
         const ColInfo ci = col_info(x, G);
         double f9[9], r, vx, vy, r0, wx, wy;
@@ -880,6 +919,7 @@ __device__ __forceinline__ void batch_residual_item(const S *cur, const S *prev,
     for (int i = threadIdx.x; i < count; i += blockDim.x) {
         const int idx = start + i;
         const int x = idx % G.nx, j = idx / G.nx;
+        if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) continue;  // fluid only
         const RowInfo ri = row_info(j, G);
         const ColInfo ci = col_info(x, G);
         double f9[9], r, vx, vy, r0, wx, wy;

@@ -110,3 +110,22 @@ def batch_sweep(n: int = 512, seed: int = DEFAULT_SEED, kinds=("cavity", "channe
         re = float(g.uniform(*re_range))
         out.append(dict(kind=kind, nx=nx, ny=ny, r=r, Re=re, U=speed))
     return out
+
+
+def rect_obstacles(nx: int, ny: int, seed: int, nbox: int = 4, wmax: int = 5, hmax: int = 5,
+                   wrap: bool = True):
+    """Seeded obstacle mask (ny, nx) of uint8 (1 = solid): nbox axis-aligned
+    rectangles of 1..wmax x 1..hmax nodes at uniform positions; with wrap they
+    may straddle the periodic seams, otherwise they are clipped."""
+    g = rng(seed)
+    m = np.zeros((ny, nx), np.uint8)
+    for _ in range(nbox):
+        w, h = int(g.integers(1, wmax + 1)), int(g.integers(1, hmax + 1))
+        x0, y0 = int(g.integers(0, nx)), int(g.integers(0, ny))
+        for j in range(y0, y0 + h):
+            for i in range(x0, x0 + w):
+                if wrap:
+                    m[j % ny, i % nx] = 1
+                elif j < ny and i < nx:
+                    m[j, i] = 1
+    return m

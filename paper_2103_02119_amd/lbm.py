@@ -27,9 +27,10 @@ LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
            "lbm_moments", "lbm_residual", "lbm_sums", "lbm_get_populations",
-           "lbm_set_populations", "lbm_steps_done", "lbm_launch_shape", "lbm_last_error",
-           "lbm_destroy")
+           "lbm_set_populations", "lbm_set_mask", "lbm_steps_done", "lbm_launch_shape",
+           "lbm_last_error", "lbm_destroy")
 BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fields",
+                 "lbm_batch_set_mask",
                  "lbm_batch_set_active", "lbm_batch_step", "lbm_batch_residuals",
                  "lbm_batch_run_to_steady", "lbm_batch_moments", "lbm_batch_get_populations",
                  "lbm_batch_set_populations", "lbm_batch_steps_done", "lbm_batch_autotune",
@@ -122,6 +123,9 @@ def load():
     L.lbm_sums.argtypes = [_CTX, _D]
     L.lbm_get_populations.argtypes = [_CTX, _D]
     L.lbm_set_populations.argtypes = [_CTX, _D]
+    _U8 = ctypes.POINTER(ctypes.c_ubyte)
+    L.lbm_set_mask.argtypes = [_CTX, _U8]
+    L.lbm_set_mask.restype = ctypes.c_int
     L.lbm_steps_done.argtypes = [_CTX]
     L.lbm_steps_done.restype = ctypes.c_long
     L.lbm_launch_shape.argtypes = [_CTX, ctypes.POINTER(ctypes.c_int),
@@ -140,6 +144,8 @@ def load():
     L.lbm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(lbm_case),
                                    ctypes.POINTER(lbm_batch_opts), ctypes.POINTER(_B)]
     L.lbm_batch_set_fields.argtypes = [_B, ctypes.c_int, _D, _D, _D]
+    L.lbm_batch_set_mask.argtypes = [_B, ctypes.c_int, _U8]
+    L.lbm_batch_set_mask.restype = ctypes.c_int
     L.lbm_batch_set_active.argtypes = [_B, _I]
     L.lbm_batch_step.argtypes = [_B, ctypes.c_long]
     L.lbm_batch_residuals.argtypes = [_B, _D]
@@ -250,6 +256,20 @@ def lbm_set_populations(ctx, nx, ny, f):
     _check(load().lbm_set_populations(ctx, p), ctx)
 
 
+def _mask(mask, shape):
+    if mask is None:
+        return None, None
+    m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+    if m.shape != shape:
+        raise ValueError(f"expected mask shape {shape}, got {m.shape}")
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+
+
+def lbm_set_mask(ctx, nx, ny, mask=None):
+    keep, p = _mask(mask, (ny, nx))
+    _check(load().lbm_set_mask(ctx, p), ctx)
+
+
 def lbm_steps_done(ctx) -> int:
     return load().lbm_steps_done(ctx)
 
@@ -325,6 +345,9 @@ class Lattice:
     def launch_shape(self):
         return lbm_launch_shape(self.ctx)
 
+    def set_mask(self, mask=None):
+        lbm_set_mask(self.ctx, self.nx, self.ny, mask)
+
     @property
     def steps_done(self):
         return lbm_steps_done(self.ctx)
@@ -384,6 +407,11 @@ def lbm_batch_create(cases, opts: lbm_batch_opts | None = None):
 def lbm_batch_set_fields(b, c, nx, ny, rho=None, ux=None, uy=None):
     keep = [_in(v, (ny, nx)) for v in (rho, ux, uy)]
     _bcheck(load().lbm_batch_set_fields(b, int(c), *[k[1] for k in keep]), b)
+
+
+def lbm_batch_set_mask(b, c, nx, ny, mask=None):
+    keep, p = _mask(mask, (ny, nx))
+    _bcheck(load().lbm_batch_set_mask(b, int(c), p), b)
 
 
 def lbm_batch_set_active(b, active):
@@ -468,6 +496,9 @@ class Batch:
 
     def set_fields(self, c, rho=None, ux=None, uy=None):
         lbm_batch_set_fields(self.b, c, *self.shapes[c], rho, ux, uy)
+
+    def set_mask(self, c, mask=None):
+        lbm_batch_set_mask(self.b, c, *self.shapes[c], mask)
 
     def set_active(self, active):
         lbm_batch_set_active(self.b, active)

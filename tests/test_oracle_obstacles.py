@@ -65,14 +65,7 @@ def test_solid_columns_are_walls_and_solid_frame_is_a_box():
 
 
 def random_mask(nx, ny, seed, nbox=4):
-    g = I.rng(seed)
-    m = np.zeros((ny, nx), np.uint8)
-    for _ in range(nbox):
-        w, h = int(g.integers(1, 6)), int(g.integers(1, 6))
-        x0, y0 = int(g.integers(0, nx)), int(g.integers(0, ny))
-        for j in range(y0, y0 + h):
-            for i in range(x0, x0 + w):
-                m[j % ny, i % nx] = 1  # boxes may straddle the periodic seams
+    m = I.rect_obstacles(nx, ny, seed, nbox)  # boxes may straddle the periodic seams
     m[3, 5] = 1  # a single solid node
     return m
 
