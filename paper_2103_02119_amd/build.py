@@ -1,8 +1,8 @@
 """Build the HIP library paper_2103_02119_amd/liblbm.so for gfx950.
 
 Compiles csrc/lbm_kernels.hip (device kernels), csrc/lbm_api.hip (the C ABI
-of include/lbm.h) and csrc/lbm_batch.hip (the batch ABI of
-include/lbm_batch.h) with hipcc into one shared library that links only
+of include/lbm.h), csrc/lbm_batch.hip (the batch ABI of include/lbm_batch.h)
+and csrc/nn_kernels.hip (the warm-start network, include/lbm_nn.h) with hipcc into one shared library that links only
 against the HIP runtime.
 """
 import os
@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_api.hip"),
-           os.path.join(CSRC, "lbm_batch.hip")]
+           os.path.join(CSRC, "lbm_batch.hip"), os.path.join(CSRC, "nn_kernels.hip")]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -12,12 +12,13 @@ from paper_2103_02119_amd import lbm as L
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
 BATCH_HEADER = os.path.join(ROOT, "include", "lbm_batch.h")
+NN_HEADER = os.path.join(ROOT, "include", "lbm_nn.h")
 
 
 def _declared_functions(header=HEADER):
     text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
+    names = set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 
@@ -31,7 +32,8 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(L.LIB_PATH)
-    for name in _declared_functions() + _declared_functions(BATCH_HEADER):
+    for name in (_declared_functions() + _declared_functions(BATCH_HEADER)
+                 + _declared_functions(NN_HEADER)):
         assert hasattr(lib, name), name
 
 
@@ -40,6 +42,22 @@ def test_binding_uses_the_same_names():
     assert sorted(L.BATCH_EXPORTS) == _declared_functions(BATCH_HEADER)
     for name in L.EXPORTS + L.BATCH_EXPORTS:
         assert callable(getattr(L, name))
+    from paper_2103_02119_amd import nn as K
+    assert sorted(K.EXPORTS) == _declared_functions(NN_HEADER)
+    for name in K.EXPORTS:
+        assert callable(getattr(K, name))
+
+
+def test_nn_rejects_bad_shapes_before_touching_the_device():
+    from paper_2103_02119_amd import nn as K
+    lib = K.load()
+    # channels not a multiple of 8, odd pooled size, missing pointers
+    assert lib.lbm_nn_conv3x3_fwd(1, 12, None, 0, 1, 8, 8, 1, 1, 32, 1, 1, None) == -1
+    assert lib.lbm_nn_conv3x3_fwd(1, 16, None, 8, 1, 8, 8, 1, 1, 32, 1, 1, None) == -1
+    assert lib.lbm_nn_conv3x3_dgrad(1, 1, 8, 8, 30, 1, 1, 16, None, 0, 0, None) == -1
+    assert lib.lbm_nn_avgpool2_fwd(1, 1, 7, 8, 4, 1, None) == -1
+    assert lib.lbm_nn_conv3x3_wgrad(1, 16, None, 0, 1, 8, 8, 1, 32, 1, 1, 1, 0, None) == -1
+    assert lib.lbm_nn_adam(1, 1, 1, 1, 10, 0.1, 0.9, 0.99, 1e-8, 0, None) == -1
 
 
 def test_required_bytes():
