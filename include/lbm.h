@@ -165,6 +165,22 @@ int lbm_set_populations(lbm_ctx *ctx, const double *f);
  * Errors: LBM_E_NOMEM, LBM_E_DEVICE. */
 int lbm_set_mask(lbm_ctx *ctx, const unsigned char *mask);
 
+/* Advances one step and replaces the state by the mean of the states before
+ * and after that step.  A mode that flips sign every step (the staggered
+ * momentum of the D2Q9 streaming: x-momentum alternating from column to
+ * column, y-momentum from row to row, which the momentum-conserving
+ * collision cannot damp) cancels exactly; smooth fields move by half a step.
+ * Meant for initial states set from macroscopic fields (lbm_set_fields
+ * excites that mode whenever the fields are not the scheme's own steady
+ * state).  Counts as one step; the residual needs a further step.
+ * Synchronizes.  Errors: LBM_E_DEVICE, LBM_E_NOMEM. */
+int lbm_smooth_step(lbm_ctx *ctx);
+
+/* Replaces the relaxation rates omega_0..omega_8 (as in lbm_create) for the
+ * following steps; the state is kept.  Synchronizes.
+ * Errors: LBM_E_INVAL (a rate outside (0, 2)), LBM_E_DEVICE. */
+int lbm_set_rates(lbm_ctx *ctx, const double rates[9]);
+
 /* Number of steps taken since creation (set_fields / set_populations do not
  * reset it). */
 long lbm_steps_done(const lbm_ctx *ctx);

@@ -74,6 +74,17 @@ int lbm_batch_set_fields(lbm_batch *b, int c, const double *rho, const double *u
  * Errors: LBM_E_INVAL (bad c), LBM_E_NOMEM, LBM_E_DEVICE. */
 int lbm_batch_set_mask(lbm_batch *b, int c, const unsigned char *mask);
 
+/* lbm_smooth_step for every active case: one batched step, then each case's
+ * state is replaced by the mean of its states before and after it.
+ * Synchronizes.  Errors: LBM_E_DEVICE, LBM_E_NOMEM. */
+int lbm_batch_smooth_step(lbm_batch *b);
+
+/* Replaces the relaxation rates of case c for the following steps (as
+ * lbm_set_rates).  A batch whose cases all had omega_6..8 = 1 at creation
+ * runs the shorter collision for them, so they must stay 1.  Synchronizes.
+ * Errors: LBM_E_INVAL, LBM_E_DEVICE. */
+int lbm_batch_set_rates(lbm_batch *b, int c, const double rates[9]);
+
 /* Marks which cases advance (active[c] != 0).  Inactive cases keep their state
  * and step count.  Takes effect for the next lbm_batch_step.
  * Errors: LBM_E_INVAL. */

@@ -554,6 +554,42 @@ extern "C" int lbm_set_mask(lbm_ctx *c, const unsigned char *mask) {
     return LBM_OK;
 }
 
+extern "C" int lbm_smooth_step(lbm_ctx *c) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    int rc = lbm_step(c, 1);
+    if (rc != LBM_OK) return rc;
+    const size_t n9 = static_cast<size_t>(9) * c->nx * c->ny;
+    rc = ensure_stage(c, n9 * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    const int p = 1 - c->cur;
+    HIP_OR_FAIL(c, launch_average_states(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
+                                         c->form[p] == kPost, c->f[p], c->d_stage, c->G, c->Kd,
+                                         c->H, c->stream));
+    HIP_OR_FAIL(c, launch_set_populations(c->prec, c->f[c->cur], c->d_stage, c->G, c->H,
+                                          c->stream));
+    c->form[c->cur] = kPre;
+    c->form[p] = kEmpty;
+    c->prev_valid = 0;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_rates(lbm_ctx *c, const double rates[9]) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!rates) return fail_ctx(c, LBM_E_INVAL, "rates is NULL");
+    for (int j = 0; j < 9; ++j)
+        if (!(rates[j] > 0.0 && rates[j] < 2.0))
+            return fail_ctx(c, LBM_E_INVAL, "rates[%d] = %g is not in (0, 2)", j, rates[j]);
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    memcpy(c->rates, rates, sizeof(c->rates));
+    c->higher_unit = rates[6] == 1.0 && rates[7] == 1.0 && rates[8] == 1.0;
+    CaseSpec spec;
+    make_spec(c->nx, c->ny, c->a, c->rates, &c->bc, &c->opts, spec);
+    fill_consts(spec, c->Kd);
+    fill_consts(spec, c->Kf);
+    return LBM_OK;
+}
+
 extern "C" long lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : 0; }
 
 extern "C" int lbm_launch_shape(const lbm_ctx *c, int *rows_per_wave, int *workgroups) {

@@ -497,6 +497,55 @@ extern "C" int lbm_batch_set_mask(lbm_batch *b, int c, const unsigned char *mask
     return upload_tiles(b);
 }
 
+extern "C" int lbm_batch_smooth_step(lbm_batch *b) {
+    if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
+    int rc = lbm_batch_step(b, 1);
+    if (rc != LBM_OK) return rc;
+    size_t most = 0;
+    for (int c = 0; c < b->n; ++c)
+        if (b->active[c]) {
+            const size_t n9 = static_cast<size_t>(9) * b->G[c].nx * b->G[c].ny;
+            most = n9 > most ? n9 : most;
+        }
+    rc = ensure_stage(b, most * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    for (int c = 0; c < b->n; ++c) {
+        if (!b->active[c]) continue;
+        const int cur = b->bc[c].cur;
+        HIP_OK(b, launch_average_states(b->prec, b->bc[c].pull != 0, case_ptr(b, c, cur),
+                                        b->form_prev[c] == kPost, case_ptr(b, c, cur ^ 1),
+                                        b->d_stage, b->G[c], b->Kd[c], b->H[c], b->stream));
+        HIP_OK(b, launch_set_populations(b->prec, case_ptr(b, c, cur), b->d_stage, b->G[c],
+                                         b->H[c], b->stream));
+        b->bc[c].pull = 0;
+        b->form_prev[c] = kEmpty;
+    }
+    HIP_OK(b, hipStreamSynchronize(b->stream));
+    return upload_cases(b);
+}
+
+extern "C" int lbm_batch_set_rates(lbm_batch *b, int c, const double rates[9]) {
+    int rc = check_case(b, c);
+    if (rc != LBM_OK) return rc;
+    if (!rates) return fail(b, LBM_E_INVAL, "rates is NULL");
+    for (int j = 0; j < 9; ++j)
+        if (!(rates[j] > 0.0 && rates[j] < 2.0))
+            return fail(b, LBM_E_INVAL, "rates[%d] = %g is not in (0, 2)", j, rates[j]);
+    if (b->higher_unit && !(rates[6] == 1.0 && rates[7] == 1.0 && rates[8] == 1.0))
+        return fail(b, LBM_E_INVAL,
+                    "this batch was built with omega_6..8 = 1 for every case; they must stay 1");
+    HIP_OK(b, hipStreamSynchronize(b->stream));
+    memcpy(b->spec[c].rates, rates, sizeof(b->spec[c].rates));
+    fill_consts(b->spec[c], b->Kd[c]);
+    fill_consts(b->spec[c], b->Kf[c]);
+    HIP_OK(b, hipMemcpyAsync(b->d_Kd + c, &b->Kd[c], sizeof(Consts<double>), hipMemcpyHostToDevice,
+                             b->stream));
+    HIP_OK(b, hipMemcpyAsync(b->d_Kf + c, &b->Kf[c], sizeof(Consts<float>), hipMemcpyHostToDevice,
+                             b->stream));
+    HIP_OK(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
 extern "C" int lbm_batch_set_active(lbm_batch *b, const int *active) {
     if (!b || !active) return fail(b, LBM_E_INVAL, "NULL argument");
     bool changed = false;

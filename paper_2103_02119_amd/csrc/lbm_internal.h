@@ -139,6 +139,10 @@ hipError_t launch_set_populations(int prec, void *dst, const double *f, const Ge
 hipError_t launch_get_populations(int prec, bool pull, const void *src, double *f,
                                   const Geometry &G, const Consts<double> &Kd,
                                   const Consts<float> &Kf, const HostSide &H, hipStream_t st);
+// f[9][n] (FP64, full populations) = mean of the states in cur and prev
+hipError_t launch_average_states(int prec, bool pull_cur, const void *cur, bool pull_prev,
+                                 const void *prev, double *f, const Geometry &G,
+                                 const Consts<double> &Kd, const HostSide &H, hipStream_t st);
 hipError_t launch_moments(int prec, bool pull, const void *src, double *rho, double *ux,
                           double *uy, const Geometry &G, const Consts<double> &Kd,
                           const Consts<float> &Kf, const HostSide &H, hipStream_t st);

@@ -794,6 +794,27 @@ __global__ void get_pop_kernel(const S *__restrict__ src, double *__restrict__ f
     }
 }
 
+// f = (state n + state n-1) / 2 in FP64 [9][n] (full populations), from the
+// current buffer (pull form PC) and the previous one (pull form PP)
+template <typename S, bool PC, bool PP>
+__global__ void avg_states_kernel(const S *__restrict__ cur, const S *__restrict__ prev,
+                                  double *__restrict__ f, const Geometry G,
+                                  const Consts<double> K, const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        const RowInfo ri = row_info(j, G);
+        const ColInfo ci = col_info(x, G);
+        double a9[9], b9[9];
+        load_node<S, double, PC>(cur, G, K, ri, ci, a9);
+        load_node<S, double, PP>(prev, G, K, ri, ci, b9);
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            f[k * n + idx] = 0.5 * (a9[k] + b9[k]) + (H.dev ? H.rho0 * H.wrest[k] : 0.0);
+    }
+}
+
 // rho, u of one node from its pre-collision values, in FP64
 __device__ __forceinline__ void macro_of(const double (&f9)[9], const HostSide &H, double &r,
                                          double &vx, double &vy) {
@@ -1048,6 +1069,28 @@ hipError_t launch_get_populations(int prec, bool pull, const void *src, double *
         if (pull) hipLaunchKernelGGL((get_pop_kernel<double, true>), grid, block, 0, st, s, f, G, Kd, H);
         else hipLaunchKernelGGL((get_pop_kernel<double, false>), grid, block, 0, st, s, f, G, Kd, H);
     }
+    return hipGetLastError();
+}
+
+template <typename S>
+static void avg_dispatch(bool pc, const S *cur, bool pp, const S *prev, double *f, const Geometry &G,
+                         const Consts<double> &Kd, const HostSide &H, hipStream_t st) {
+    const dim3 grid(conv_blocks(G)), block(256);
+    if (pc && pp) hipLaunchKernelGGL((avg_states_kernel<S, true, true>), grid, block, 0, st, cur, prev, f, G, Kd, H);
+    else if (pc) hipLaunchKernelGGL((avg_states_kernel<S, true, false>), grid, block, 0, st, cur, prev, f, G, Kd, H);
+    else if (pp) hipLaunchKernelGGL((avg_states_kernel<S, false, true>), grid, block, 0, st, cur, prev, f, G, Kd, H);
+    else hipLaunchKernelGGL((avg_states_kernel<S, false, false>), grid, block, 0, st, cur, prev, f, G, Kd, H);
+}
+
+hipError_t launch_average_states(int prec, bool pull_cur, const void *cur, bool pull_prev,
+                                 const void *prev, double *f, const Geometry &G,
+                                 const Consts<double> &Kd, const HostSide &H, hipStream_t st) {
+    if (f32_storage(prec))
+        avg_dispatch<float>(pull_cur, static_cast<const float *>(cur), pull_prev,
+                            static_cast<const float *>(prev), f, G, Kd, H, st);
+    else
+        avg_dispatch<double>(pull_cur, static_cast<const double *>(cur), pull_prev,
+                             static_cast<const double *>(prev), f, G, Kd, H, st);
     return hipGetLastError();
 }
 

@@ -129,3 +129,27 @@ def rect_obstacles(nx: int, ny: int, seed: int, nbox: int = 4, wmax: int = 5, hm
                 elif j < ny and i < nx:
                     m[j, i] = 1
     return m
+
+
+def cavity_obstacles(nx: int, ny: int, seed: int, nmax: int = 3, margin: int = 4,
+                     lid_gap: int = 12):
+    """Seeded obstacles for a lid-driven cavity: 1..nmax axis-aligned boxes
+    of nx/32..nx/4 by ny/16..ny/3 nodes, kept `margin` nodes from the walls
+    and `lid_gap` rows below the lid.  Returns a (ny, nx) uint8 mask."""
+    g = rng(seed)
+    m = np.zeros((ny, nx), np.uint8)
+    for _ in range(int(g.integers(1, nmax + 1))):
+        w = int(g.integers(max(2, nx // 32), max(3, nx // 4) + 1))
+        h = int(g.integers(max(2, ny // 16), max(3, ny // 3) + 1))
+        x0 = int(g.integers(margin, max(margin + 1, nx - margin - w)))
+        y0 = int(g.integers(margin, max(margin + 1, ny - lid_gap - h)))
+        m[y0:y0 + h, x0:x0 + w] = 1
+    return m
+
+
+def warmstart_cases(n: int, seed: int = DEFAULT_SEED, re_range=(100.0, 5000.0),
+                    ratios=(0.25, 0.5, 1.0)):
+    """Seeded (Re, r, obstacle seed) parameters of n cavity cases."""
+    g = rng(seed)
+    return [dict(Re=float(g.uniform(*re_range)), r=float(ratios[int(g.integers(len(ratios)))]),
+                 mask_seed=int(g.integers(1 << 30))) for _ in range(n)]

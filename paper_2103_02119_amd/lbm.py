@@ -27,10 +27,12 @@ LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
            "lbm_moments", "lbm_residual", "lbm_sums", "lbm_get_populations",
-           "lbm_set_populations", "lbm_set_mask", "lbm_steps_done", "lbm_launch_shape",
+           "lbm_set_populations", "lbm_set_mask", "lbm_set_rates", "lbm_smooth_step",
+           "lbm_steps_done",
+           "lbm_launch_shape",
            "lbm_last_error", "lbm_destroy")
 BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fields",
-                 "lbm_batch_set_mask",
+                 "lbm_batch_set_mask", "lbm_batch_set_rates", "lbm_batch_smooth_step",
                  "lbm_batch_set_active", "lbm_batch_step", "lbm_batch_residuals",
                  "lbm_batch_run_to_steady", "lbm_batch_moments", "lbm_batch_get_populations",
                  "lbm_batch_set_populations", "lbm_batch_steps_done", "lbm_batch_autotune",
@@ -126,6 +128,10 @@ def load():
     _U8 = ctypes.POINTER(ctypes.c_ubyte)
     L.lbm_set_mask.argtypes = [_CTX, _U8]
     L.lbm_set_mask.restype = ctypes.c_int
+    L.lbm_set_rates.argtypes = [_CTX, _D]
+    L.lbm_set_rates.restype = ctypes.c_int
+    L.lbm_smooth_step.argtypes = [_CTX]
+    L.lbm_smooth_step.restype = ctypes.c_int
     L.lbm_steps_done.argtypes = [_CTX]
     L.lbm_steps_done.restype = ctypes.c_long
     L.lbm_launch_shape.argtypes = [_CTX, ctypes.POINTER(ctypes.c_int),
@@ -146,6 +152,10 @@ def load():
     L.lbm_batch_set_fields.argtypes = [_B, ctypes.c_int, _D, _D, _D]
     L.lbm_batch_set_mask.argtypes = [_B, ctypes.c_int, _U8]
     L.lbm_batch_set_mask.restype = ctypes.c_int
+    L.lbm_batch_set_rates.argtypes = [_B, ctypes.c_int, _D]
+    L.lbm_batch_set_rates.restype = ctypes.c_int
+    L.lbm_batch_smooth_step.argtypes = [_B]
+    L.lbm_batch_smooth_step.restype = ctypes.c_int
     L.lbm_batch_set_active.argtypes = [_B, _I]
     L.lbm_batch_step.argtypes = [_B, ctypes.c_long]
     L.lbm_batch_residuals.argtypes = [_B, _D]
@@ -270,6 +280,15 @@ def lbm_set_mask(ctx, nx, ny, mask=None):
     _check(load().lbm_set_mask(ctx, p), ctx)
 
 
+def lbm_smooth_step(ctx):
+    _check(load().lbm_smooth_step(ctx), ctx)
+
+
+def lbm_set_rates(ctx, rates):
+    arr = (ctypes.c_double * 9)(*[float(w) for w in rates])
+    _check(load().lbm_set_rates(ctx, arr), ctx)
+
+
 def lbm_steps_done(ctx) -> int:
     return load().lbm_steps_done(ctx)
 
@@ -348,6 +367,12 @@ class Lattice:
     def set_mask(self, mask=None):
         lbm_set_mask(self.ctx, self.nx, self.ny, mask)
 
+    def set_rates(self, rates):
+        lbm_set_rates(self.ctx, rates)
+
+    def smooth_step(self):
+        lbm_smooth_step(self.ctx)
+
     @property
     def steps_done(self):
         return lbm_steps_done(self.ctx)
@@ -412,6 +437,15 @@ def lbm_batch_set_fields(b, c, nx, ny, rho=None, ux=None, uy=None):
 def lbm_batch_set_mask(b, c, nx, ny, mask=None):
     keep, p = _mask(mask, (ny, nx))
     _bcheck(load().lbm_batch_set_mask(b, int(c), p), b)
+
+
+def lbm_batch_smooth_step(b):
+    _bcheck(load().lbm_batch_smooth_step(b), b)
+
+
+def lbm_batch_set_rates(b, c, rates):
+    arr = (ctypes.c_double * 9)(*[float(w) for w in rates])
+    _bcheck(load().lbm_batch_set_rates(b, int(c), arr), b)
 
 
 def lbm_batch_set_active(b, active):
@@ -499,6 +533,12 @@ class Batch:
 
     def set_mask(self, c, mask=None):
         lbm_batch_set_mask(self.b, c, *self.shapes[c], mask)
+
+    def set_rates(self, c, rates):
+        lbm_batch_set_rates(self.b, c, rates)
+
+    def smooth_step(self):
+        lbm_batch_smooth_step(self.b)
 
     def set_active(self, active):
         lbm_batch_set_active(self.b, active)

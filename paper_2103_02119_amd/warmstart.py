@@ -4,7 +4,7 @@ A 4-level convolutional encoder-decoder (32, 64, 128, 256 channels; skip
 connections by channel concatenation; 2 x 2 average pooling down, nearest
 upsampling up; two 3x3 ReLU convolutions per level and a 1x1 head) maps
   input  (per node): solid flag, Re, aspect ratio a, x / W, y / H (BF16)
-  output (per node): (rho - 1) / s_rho, ux / U, uy / U           (FP32)
+  output (per node): (rho - 1) cs2 / U^2, ux / U, uy / U          (FP32)
 for lid-driven cavities with rectangular obstacles.  Its prediction is the
 initial state of the lattice (lbm_set_fields); the lattice Boltzmann run
 then converges from it, so the scheme itself decides the answer and the
@@ -271,22 +271,26 @@ def input_planes(mask, Re, a):
 
 
 class Scales:
-    """Output normalization: (rho - 1) / s_rho, u / U."""
+    """Output normalization: the pressure coefficient (rho - 1) cs2 / U^2
+    (p = rho cs2) and u / U; cs2 differs between aspect ratios, the pressure
+    coefficient does not."""
 
-    def __init__(self, s_rho, U):
-        self.s_rho, self.U = float(s_rho), float(U)
+    def __init__(self, U):
+        self.U = float(U)
 
-    def encode(self, rho, ux, uy):
-        return np.stack([(rho - 1.0) / self.s_rho, ux / self.U, uy / self.U], -1).astype(np.float32)
+    def encode(self, rho, ux, uy, cs2):
+        c = np.asarray(cs2, np.float64).reshape(-1, *([1] * (rho.ndim - 1))) if rho.ndim == 3 else cs2
+        return np.stack([(rho - 1.0) * c / self.U ** 2, ux / self.U, uy / self.U], -1).astype(np.float32)
 
-    def decode(self, y):
-        return 1.0 + self.s_rho * y[..., 0], self.U * y[..., 1], self.U * y[..., 2]
+    def decode(self, y, cs2):
+        return 1.0 + y[..., 0] * self.U ** 2 / cs2, self.U * y[..., 1], self.U * y[..., 2]
 
 
 def cavity_cases(params, nx, ny, U):
-    """lbm_case list for dicts with keys Re, r (lid-driven cavities)."""
+    """lbm_case list for dicts with keys Re, r (lid-driven cavities, the
+    sound speed of the paper's cavity runs)."""
     from . import workloads as Wk
-    return [Wk.cavity_case(nx, ny, p["r"], p["Re"], U) for p in params]
+    return [Wk.cavity_case(nx, ny, p["r"], p["Re"], U, cs2=Wk.cavity_cs2(p["r"])) for p in params]
 
 
 def generate(params, masks, nx, ny, U, precision, tol, check_every, max_steps, log=None):
@@ -387,3 +391,179 @@ def predict_raw(net, X):
     x = t.from_numpy(xb).cuda().reshape(-1)
     y = net.forward(x)
     return y.reshape(N, H, W, COUT)[:n].cpu().numpy()
+
+
+# ---------------------------------------------------------------- pipeline
+
+def _log_default(msg):
+    print(msg, flush=True)
+
+
+def build_dataset(params, nx=256, ny=128, U=0.05, precision=L.LBM_FP32_DEV, tol=2e-6,
+                  check_every=1000, max_steps=150_000, log=_log_default):
+    """Steady cavity fields for the given case parameters (dicts Re, r,
+    mask_seed) from the batched solver; keeps the converged cases.  Returns
+    (X [n, ny, nx, CIN], fields (rho, ux, uy) [n, ny, nx] each, masks, kept
+    parameter dicts, generation info)."""
+    from . import inputs as I
+
+    masks = [I.cavity_obstacles(nx, ny, p["mask_seed"]) for p in params]
+    rho, ux, uy, steps, wall = generate(params, masks, nx, ny, U, precision, tol, check_every,
+                                        max_steps, log=log)
+    keep = np.nonzero(steps > 0)[0]
+    X = np.stack([input_planes(masks[i], params[i]["Re"], params[i]["r"]) for i in keep])
+    info = dict(cases=len(params), converged=int(len(keep)), blew_up=int((steps == -1).sum()),
+                not_converged=int((steps == -2).sum()), seconds=round(wall, 2), tol=tol,
+                median_steps=int(np.median(steps[keep])) if len(keep) else None)
+    return X, (rho[keep], ux[keep], uy[keep]), [masks[i] for i in keep], [params[i] for i in keep], info
+
+
+def train(net, X, T, F, epochs, lr_max=1e-3, lr_min=2e-5, val=None, channel_weights=(0.25, 1, 1),
+          log=_log_default):
+    """Adam with a cosine learning-rate schedule; returns the loss history.
+    The pressure channel is weighted down: an initial density error costs
+    the lattice run little, a velocity error much more."""
+    tr = Trainer(net, X, T, F)
+    tr.cw.copy_(net.torch.tensor(channel_weights, dtype=net.torch.float32))
+    hist = []
+    t0 = time.perf_counter()
+    for e in range(epochs):
+        lr = lr_min + 0.5 * (lr_max - lr_min) * (1 + np.cos(np.pi * e / max(epochs - 1, 1)))
+        loss = tr.epoch(lr)
+        rec = dict(epoch=e, lr=float(lr), loss=loss)
+        if val is not None and (e % 10 == 9 or e == epochs - 1):
+            rec["val"] = tr.evaluate(*val)
+        hist.append(rec)
+        if e % 10 == 9 or e == epochs - 1:
+            log(f"train: epoch {e + 1}/{epochs} loss {loss:.4g}"
+                + (f" val {rec['val']:.4g}" if "val" in rec else "") + f" {time.perf_counter() - t0:.1f} s")
+    return hist, time.perf_counter() - t0
+
+
+def predict_fields(net, scales, masks, params):
+    """Predicted (rho, ux, uy) [ny, nx] per case; solid nodes at rest."""
+    out = []
+    X = np.stack([input_planes(m, p["Re"], p["r"]) for m, p in zip(masks, params)])
+    for s in range(0, len(X), net.N):
+        y = predict_raw(net, X[s:s + net.N])
+        from . import workloads as Wk
+        for j in range(y.shape[0]):
+            rho, ux, uy = scales.decode(y[j].astype(np.float64), Wk.cavity_cs2(params[s + j]["r"]))
+            solid = masks[s + j] != 0
+            rho[solid], ux[solid], uy[solid] = 1.0, 0.0, 0.0
+            out.append((rho, ux, uy))
+    return out
+
+
+SETTLE_STEPS = 50   # steps before the smoothing step of a start from fields
+
+
+def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_every=1000,
+                 max_steps=400_000, log=_log_default):
+    """Steps and wall time to a per-step residual of tol (FP64, the plain
+    lattice Boltzmann scheme as judge) for the same cases started
+      cold        from rest,
+      cold+smooth from rest, with one smoothing step after SETTLE_STEPS,
+      warm        from the network's prediction (lbm_set_fields),
+      warm+smooth from the prediction, with the smoothing step.
+    An equilibrium start from any field that is not the scheme's own steady
+    state excites the undamped staggered-momentum mode of the D2Q9 streaming;
+    the smoothing step (mean of two consecutive states) removes it.  Each
+    variant advances all cases as one batch."""
+    import torch
+
+    from . import inputs as I
+
+    masks = [I.cavity_obstacles(nx, ny, p["mask_seed"]) for p in params]
+    res = {}
+    for mode in ("cold", "cold+smooth", "warm", "warm+smooth"):
+        b = L.Batch(cavity_cases(params, nx, ny, U), precision=L.LBM_FP64)
+        for c, m in enumerate(masks):
+            b.set_mask(c, m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode.startswith("warm"):
+            for c, (rho, ux, uy) in enumerate(predict_fields(net, scales, masks, params)):
+                b.set_fields(c, rho, ux, uy)
+        t_inf = time.perf_counter() - t0
+        extra = 0
+        if mode.endswith("smooth"):
+            b.step(SETTLE_STEPS)
+            b.smooth_step()
+            extra = SETTLE_STEPS + 1
+        steps = b.run_to_steady(tol, check_every, max_steps)
+        steps = np.where(steps > 0, steps + extra, steps)
+        wall = time.perf_counter() - t0
+        b.close()
+        res[mode] = dict(steps=steps, seconds=wall, inference_seconds=t_inf)
+        log(f"{mode}: {int((steps > 0).sum())}/{len(params)} reached {tol:g} in {wall:.1f} s")
+    out = dict(tol=tol, cases=len(params), settle_steps=SETTLE_STEPS,
+               inference_seconds=round(res["warm+smooth"]["inference_seconds"], 3))
+    for mode, r in res.items():
+        out[mode] = dict(reached=int((r["steps"] > 0).sum()), seconds=round(r["seconds"], 3))
+    ref = "cold"
+    for mode in ("cold+smooth", "warm", "warm+smooth"):
+        both = (res[ref]["steps"] > 0) & (res[mode]["steps"] > 0)
+        sc, sw = res[ref]["steps"][both], res[mode]["steps"][both]
+        out[mode].update(compared=int(both.sum()), steps_total=int(sw.sum()),
+                         cold_steps_total=int(sc.sum()),
+                         step_speedup_total=float(sc.sum() / max(sw.sum(), 1)),
+                         step_speedup_median=float(np.median(sc / sw)) if len(sc) else None)
+    out["wall_speedup_warm_smooth_vs_cold"] = float(res["cold"]["seconds"] / res["warm+smooth"]["seconds"])
+    out["per_case"] = [dict(Re=round(p["Re"], 1), r=p["r"],
+                            **{m: int(res[m]["steps"][c]) for m in res}) for c, p in enumerate(params)]
+    return out
+
+
+def run_pipeline(n_train=2048, n_test=64, epochs=150, batch=16, seed=2103, test_seed=77,
+                 out_dir=None, log=_log_default):
+    """Generate steady fields with the batched solver, train the network on
+    them, then compare cold and warm starts on unseen cases."""
+    import json
+    import os
+
+    from . import inputs as I
+
+    t0 = time.perf_counter()
+    params = I.warmstart_cases(n_train, seed=seed)
+    X, (rho, ux, uy), masks, kept, gen_info = build_dataset(params, log=log)
+    log(f"dataset: {gen_info}")
+    from . import workloads as Wk
+
+    fluid = (X[..., 0] == 0).astype(np.uint8)
+    scales = Scales(0.05)
+    T = scales.encode(rho, ux, uy, [Wk.cavity_cs2(p["r"]) for p in kept])
+    nval = max(batch, len(X) // 10)
+    net = WarmStartNet(H=X.shape[1], W=X.shape[2], batch=batch, seed=seed)
+    hist, t_train = train(net, X[nval:], T[nval:], fluid[nval:], epochs,
+                          val=(X[:nval], T[:nval], fluid[:nval]), log=log)
+    test = I.warmstart_cases(n_test, seed=test_seed)
+    cmp = warm_vs_cold(net, scales, test, log=log)
+    metrics = dict(dataset=gen_info, train_samples=int(len(X) - nval),
+                   val_samples=int(nval), epochs=epochs, batch=batch,
+                   train_seconds=round(t_train, 2), final_loss=hist[-1]["loss"],
+                   final_val=hist[-1].get("val"), warm_vs_cold=cmp,
+                   total_seconds=round(time.perf_counter() - t0, 1))
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        np.savez_compressed(os.path.join(out_dir, "warmstart_weights.npz"), U=scales.U,
+                            **{k: v.astype(np.float32) for k, v in net.state().items()})
+        with open(os.path.join(out_dir, "warmstart_metrics.json"), "w") as fh:
+            json.dump(dict(metrics, history=hist), fh, indent=1)
+    return metrics, net, scales
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
+    ap.add_argument("--train-cases", type=int, default=2048)
+    ap.add_argument("--test-cases", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    m, _, _ = run_pipeline(a.train_cases, a.test_cases, a.epochs, out_dir=a.out)
+    m = dict(m)
+    m["warm_vs_cold"] = {k: v for k, v in m["warm_vs_cold"].items() if k != "per_case"}
+    print(json.dumps(m), flush=True)

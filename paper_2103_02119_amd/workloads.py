@@ -2,9 +2,9 @@
 
 The relaxation rates follow the paper's choice (Sec. 2.3): omega_4 = omega_5
 = 1/tau with nu = cs2 (tau - 1/2) (Eq. 32), every other rate 1.  The default
-cs2 is min(1/3, 0.64 a^2), the rule that reproduces the paper's tables at
-a = 1, 0.5 and 0.25 (cs2 must stay below min(1, a^2) for positive rest
-weights).
+cs2 is min(1/3, 0.64 a^2), the rule of the paper's channel runs (Table 1) at
+a = 1, 0.5 and 0.25; its cavity runs (Table 3) use cavity_cs2.  cs2 must
+stay below min(1, a^2) for positive rest weights.
 """
 from __future__ import annotations
 
@@ -13,6 +13,12 @@ from . import lbm as L
 
 def default_cs2(a: float) -> float:
     return min(1.0 / 3.0, 0.64 * a * a)
+
+
+def cavity_cs2(a: float) -> float:
+    """Squared sound speed of the paper's cavity runs (Table 3): 1/3 on the
+    square lattice, 0.04 at a = 0.5 and a = 0.25 (min(0.04, 0.64 a^2) below 1)."""
+    return 1.0 / 3.0 if a >= 1.0 else min(0.04, 0.64 * a * a)
 
 
 def paper_rates(nu: float, cs2: float):

@@ -236,3 +236,29 @@ def test_full_sweep_512_cases_sampled():
     for i, j in [(0, 0), (k.nx - 1, k.ny - 1), (k.nx // 2, k.ny // 2), (1, k.ny - 1), (k.nx - 1, 1)]:
         assert np.abs(got[:, j, i] - O.step_node(p, f_before, i, j)).max() / scale < 1e-6
     b.close()
+
+
+def test_batch_smooth_step_and_set_rates_match_single_lattices():
+    announce("batch smooth step")
+    b = L.Batch(cases_of(SPECS, GENERAL), graph_steps=4)
+    b.step(5)
+    b.set_rates(2, [1.0, 0.8, 1.1, 1.2, 1.4, 1.4, 0.9, 1.1, 1.3])
+    b.smooth_step()
+    b.step(6)
+    for c, spec in enumerate(SPECS):
+        lat = single(spec, L.LBM_RC, L.LBM_FP64, GENERAL)
+        lat.step(5)
+        if c == 2:
+            lat.set_rates([1.0, 0.8, 1.1, 1.2, 1.4, 1.4, 0.9, 1.1, 1.3])
+        lat.smooth_step()
+        lat.step(6)
+        assert np.array_equal(b.get_populations(c), lat.get_populations()), c
+        assert b.steps_done(c) == 12
+        lat.close()
+    b.close()
+    # a batch built for omega_6..8 = 1 keeps them
+    b = L.Batch(cases_of(SPECS[:2]))
+    with pytest.raises(L.LbmError) as e:
+        b.set_rates(0, GENERAL)
+    assert e.value.code == L.LBM_E_INVAL
+    b.close()

@@ -420,3 +420,44 @@ def test_full_size_shear_layer_2048x8192_sampled(prec, tol):
     lat.step(1)
     _sampled_check(p, lat, f_before, tol, nsamp=40)
     lat.close()
+
+
+# ---------------------------------------------------------------- state operations
+
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP64_DEV])
+@pytest.mark.parametrize("name", ["cavity", "periodic"])
+def test_smooth_step_is_the_mean_of_two_steps(name, prec):
+    nx, ny = 150, 70
+    announce("smooth step", name, prec)
+    p, lat = make(name, nx, ny, prec=prec)
+    f0 = random_state(p, seed=61)
+    lat.set_populations(f0)
+    lat.step(3)
+    lat.smooth_step()
+    f3 = O.run(p, f0, 3)
+    expect = 0.5 * (f3 + O.run(p, f3, 1))
+    assert rel(lat.get_populations(), expect) < TOL64
+    assert lat.steps_done == 4
+    with pytest.raises(L.LbmError):
+        lat.residual()
+    lat.step(2)
+    assert rel(lat.get_populations(), O.run(p, expect, 2)) < TOL64
+    lat.close()
+
+
+def test_set_rates_between_steps():
+    nx, ny = 97, 45
+    a, cs2, bc, uw, F = CASES["cavity"]
+    pA = O.make_params(nx, ny, a, cs2, RATES_HU, bc=bc, u_wall=uw)
+    pB = O.make_params(nx, ny, a, cs2, RATES_GEN, bc=bc, u_wall=uw)
+    lat = L.Lattice(nx, ny, a, RATES_HU, bc_types=bc, u_wall=uw, cs2=cs2)
+    f0 = random_state(pA, seed=62)
+    lat.set_populations(f0)
+    lat.step(2)
+    lat.set_rates(RATES_GEN)
+    lat.step(3)
+    assert rel(lat.get_populations(), O.run(pB, O.run(pA, f0, 2), 3)) < TOL64
+    with pytest.raises(L.LbmError) as e:
+        lat.set_rates([1.0] * 8 + [2.0])
+    assert e.value.code == L.LBM_E_INVAL
+    lat.close()
