@@ -56,6 +56,7 @@ struct lbm_batch {
     int *d_ntiles;
     int tile_cap;
     int ntiles;
+    bool tiles_dirty;           // the tile list must be rebuilt before the next launch
     BatchRed *d_items;
     int item_cap;
     int *d_case_first, *d_case_count;
@@ -130,6 +131,13 @@ static int upload_tiles(lbm_batch *b) {
     return LBM_OK;
 }
 
+static int ensure_tiles(lbm_batch *b) {
+    if (!b->tiles_dirty) return LBM_OK;
+    int rc = upload_tiles(b);
+    if (rc == LBM_OK) b->tiles_dirty = false;
+    return rc;
+}
+
 static int upload_cases(lbm_batch *b) {
     HIP_OK(b, hipMemcpyAsync(b->d_cases, b->bc.data(), b->n * sizeof(BatchCase),
                              hipMemcpyHostToDevice, b->stream));
@@ -154,7 +162,9 @@ static int apply_rows(lbm_batch *b, int rows) {
     HIP_OK(b, hipMemcpyAsync(b->d_geoms, b->G.data(), b->n * sizeof(Geometry),
                              hipMemcpyHostToDevice, b->stream));
     b->graph_ok = false;
-    return upload_tiles(b);
+    int rc = upload_tiles(b);
+    if (rc == LBM_OK) b->tiles_dirty = false;
+    return rc;
 }
 
 static hipError_t launch(lbm_batch *b, int flip, int force_pull, int wgs) {
@@ -494,7 +504,9 @@ extern "C" int lbm_batch_set_mask(lbm_batch *b, int c, const unsigned char *mask
     }
     HIP_OK(b, hipMemcpyAsync(b->d_geoms + c, &G, sizeof(Geometry), hipMemcpyHostToDevice,
                              b->stream));
-    return upload_tiles(b);
+    HIP_OK(b, hipStreamSynchronize(b->stream));
+    b->tiles_dirty = true;  // rebuilt (once) before the next launch
+    return LBM_OK;
 }
 
 extern "C" int lbm_batch_smooth_step(lbm_batch *b) {
@@ -554,7 +566,8 @@ extern "C" int lbm_batch_set_active(lbm_batch *b, const int *active) {
         if (a != b->active[c]) changed = true;
         b->active[c] = a;
     }
-    return changed ? upload_tiles(b) : LBM_OK;
+    if (changed) b->tiles_dirty = true;
+    return LBM_OK;
 }
 
 // Host bookkeeping after `n` steps of every active case.
@@ -572,6 +585,8 @@ static void commit_steps(lbm_batch *b, long n) {
 extern "C" int lbm_batch_step(lbm_batch *b, long n) {
     if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
     if (n < 0) return fail(b, LBM_E_INVAL, "n must be >= 0");
+    int trc = ensure_tiles(b);
+    if (trc != LBM_OK) return trc;
     if (n == 0 || b->ntiles == 0) return LBM_OK;
     // first step of cases still in place: one launch reading the per-case
     // forms, then every active case is in pull form
@@ -763,7 +778,13 @@ extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, in
     if (!b) return LBM_E_INVAL;
     if (rows_per_wave) *rows_per_wave = b->rows;
     if (workgroups) *workgroups = b->workgroups;
-    if (tiles) *tiles = b->ntiles;
+    if (tiles) {
+        // count without touching the device when the list is stale
+        int t = 0;
+        for (int c = 0; c < b->n; ++c)
+            if (b->active[c]) t += b->G[c].ntile;
+        *tiles = t;
+    }
     return LBM_OK;
 }
 

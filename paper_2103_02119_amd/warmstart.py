@@ -3,7 +3,8 @@
 A 4-level convolutional encoder-decoder (32, 64, 128, 256 channels; skip
 connections by channel concatenation; 2 x 2 average pooling down, nearest
 upsampling up; two 3x3 ReLU convolutions per level and a 1x1 head) maps
-  input  (per node): solid flag, Re, aspect ratio a, x / W, y / H (BF16)
+  input  (per node): solid flag, Re, aspect ratio a, x / W, y / H,
+                     distance to the nearest solid or wall         (BF16)
   output (per node): (rho - 1) cs2 / U^2, ux / U, uy / U          (FP32)
 for lid-driven cavities with rectangular obstacles.  Its prediction is the
 initial state of the lattice (lbm_set_fields); the lattice Boltzmann run
@@ -24,7 +25,7 @@ from . import lbm as L
 from . import nn as K
 
 LEVELS = (32, 64, 128, 256)
-CIN = 8          # solid, Re, a, x, y and three zero channels (3x3 layers need multiples of 8)
+CIN = 8          # solid, Re, a, x, y, wall distance and two zero channels (multiples of 8)
 COUT = 3
 RE_MID, RE_HALF = 2550.0, 2450.0   # Re in [100, 5000] -> [-1, 1]
 
@@ -257,9 +258,23 @@ class WarmStartNet:
 
 # ---------------------------------------------------------------- data
 
+def wall_distance(mask, a):
+    """Distance (lattice x units) from each node to the nearest solid node or
+    cavity wall (walls half a node beyond the outer rows and columns)."""
+    from scipy.ndimage import distance_transform_edt
+
+    H, W = mask.shape
+    fluid = np.zeros((H + 2, W + 2), bool)
+    fluid[1:-1, 1:-1] = mask == 0
+    d = distance_transform_edt(fluid, sampling=(a, 1.0))[1:-1, 1:-1]
+    # a wall lies half a spacing from the outer nodes, not a full one
+    return np.maximum(d - 0.5 * min(a, 1.0), 0.0) * (mask == 0)
+
+
 def input_planes(mask, Re, a):
     """FP32 [H, W, CIN] network input of one case: solid flag, normalized Re
-    and aspect ratio, node coordinates in [0, 1], zero padding."""
+    and aspect ratio, node coordinates in [0, 1], distance to the nearest
+    solid or wall (/32), zero padding."""
     H, W = mask.shape
     x = np.zeros((H, W, CIN), np.float32)
     x[..., 0] = mask != 0
@@ -267,6 +282,7 @@ def input_planes(mask, Re, a):
     x[..., 2] = (a - 0.5) / 0.5
     x[..., 3] = (np.arange(W, dtype=np.float32)[None, :] + 0.5) / W
     x[..., 4] = (np.arange(H, dtype=np.float32)[:, None] + 0.5) / H
+    x[..., 5] = wall_distance(mask, a) / 32.0
     return x
 
 
@@ -298,10 +314,14 @@ def generate(params, masks, nx, ny, U, precision, tol, check_every, max_steps, l
     Returns (rho, ux, uy) arrays [n, ny, nx], the per-case steps (-1 blown up,
     -2 not converged at max_steps) and the wall time."""
     cases = cavity_cases(params, nx, ny, U)
+    t0 = time.perf_counter()
     b = L.Batch(cases, precision=precision)
     for c, m in enumerate(masks):
         b.set_mask(c, m)
     b.autotune(2)
+    if log:
+        log(f"generate: {len(cases)} cases set up in {time.perf_counter() - t0:.1f} s, "
+            f"launch shape {b.launch_shape()}")
     t0 = time.perf_counter()
     steps = np.full(len(cases), -2, np.int64)
     done = 0
@@ -515,8 +535,9 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
     return out
 
 
-def run_pipeline(n_train=2048, n_test=64, epochs=150, batch=16, seed=2103, test_seed=77,
-                 out_dir=None, log=_log_default):
+def run_pipeline(n_train=3200, n_test=64, epochs=120, batch=16, seed=2103, test_seed=77,
+                 out_dir=None, nx=256, ny=128, gen_max_steps=150_000, eval_max_steps=400_000,
+                 re_range=(100.0, 5000.0), log=_log_default):
     """Generate steady fields with the batched solver, train the network on
     them, then compare cold and warm starts on unseen cases."""
     import json
@@ -525,8 +546,9 @@ def run_pipeline(n_train=2048, n_test=64, epochs=150, batch=16, seed=2103, test_
     from . import inputs as I
 
     t0 = time.perf_counter()
-    params = I.warmstart_cases(n_train, seed=seed)
-    X, (rho, ux, uy), masks, kept, gen_info = build_dataset(params, log=log)
+    params = I.warmstart_cases(n_train, seed=seed, re_range=re_range)
+    X, (rho, ux, uy), masks, kept, gen_info = build_dataset(params, nx=nx, ny=ny,
+                                                            max_steps=gen_max_steps, log=log)
     log(f"dataset: {gen_info}")
     from . import workloads as Wk
 
@@ -537,8 +559,8 @@ def run_pipeline(n_train=2048, n_test=64, epochs=150, batch=16, seed=2103, test_
     net = WarmStartNet(H=X.shape[1], W=X.shape[2], batch=batch, seed=seed)
     hist, t_train = train(net, X[nval:], T[nval:], fluid[nval:], epochs,
                           val=(X[:nval], T[:nval], fluid[:nval]), log=log)
-    test = I.warmstart_cases(n_test, seed=test_seed)
-    cmp = warm_vs_cold(net, scales, test, log=log)
+    test = I.warmstart_cases(n_test, seed=test_seed, re_range=re_range)
+    cmp = warm_vs_cold(net, scales, test, nx=nx, ny=ny, max_steps=eval_max_steps, log=log)
     metrics = dict(dataset=gen_info, train_samples=int(len(X) - nval),
                    val_samples=int(nval), epochs=epochs, batch=batch,
                    train_seconds=round(t_train, 2), final_loss=hist[-1]["loss"],
@@ -558,9 +580,9 @@ if __name__ == "__main__":
     import json
 
     ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
-    ap.add_argument("--train-cases", type=int, default=2048)
+    ap.add_argument("--train-cases", type=int, default=3200)
     ap.add_argument("--test-cases", type=int, default=64)
-    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     m, _, _ = run_pipeline(a.train_cases, a.test_cases, a.epochs, out_dir=a.out)
