@@ -102,6 +102,7 @@ def lib():
             "orc_run": [P, _D, _D, ctypes.c_long],
             "orc_step_node": [P, _D, ctypes.c_int, ctypes.c_int, _D],
             "orc_moments": [P, _D, _D, _D, _D],
+            "orc_stress": [P, _D, _D, _D, _D],
             "orc_set_threads": [ctypes.c_int],
         }
         for name, argtypes in sigs.items():
@@ -243,3 +244,11 @@ def set_threads(n):
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+def stress(p, f):
+    """Local viscous stress (tau_xx, tau_yy, tau_xy), each (ny, nx)."""
+    f = _f64(f)
+    out = [np.zeros((p.ny, p.nx)) for _ in range(3)]
+    lib().orc_stress(ctypes.byref(p), _ptr(f), *[_ptr(o) for o in out])
+    return tuple(out)

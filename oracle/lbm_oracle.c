@@ -528,6 +528,50 @@ void orc_run(const orc_params *p, double *f, double *work, long nsteps)
         free(ft);
 }
 
+/* Local viscous stress of every node (Sec. 4 stress output): the strain
+ * rate of Eq. 37-38 (d_x u_x, d_y u_y) and Eq. 39 read as
+ * d_y u_x + d_x u_y = (eta_xy - m_5^{eq,r}) / D_1, D_1 = -rho cs2 / omega_5,
+ * with the raw non-equilibrium moments of Eq. 34-36; then the viscous terms
+ * of Eq. 30-31: tau_xx = rho [nu (2 d_x u_x - div u) + zeta div u], tau_yy
+ * likewise, tau_xy = rho nu (d_y u_x + d_x u_y), nu from omega_4 / omega_5
+ * (Eq. 32), zeta from omega_3 (Eq. 33).  Solid nodes get 0. */
+void orc_stress(const orc_params *p, const double *f, double *sxx, double *syy, double *sxy)
+{
+    const size_t n = (size_t)p->nx * p->ny;
+    double *rho = malloc(n * sizeof(double));
+    double *gx = malloc(n * sizeof(double));
+    double *gy = malloc(n * sizeof(double));
+    double T[81];
+    orc_T(p->a, T);
+    orc_density(p, f, rho);
+    orc_density_gradient(p, rho, gx, gy);
+    const double s = p->cs2;
+    const double nu4 = s * (1.0 / p->omega[4] - 0.5), nu5 = s * (1.0 / p->omega[5] - 0.5);
+    const double zeta = s * (1.0 / p->omega[3] - 0.5);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            const size_t q = IDX(p, j, i);
+            if (is_solid(p, i, j)) {
+                sxx[q] = syy[q] = sxy[q] = 0.0;
+                continue;
+            }
+            double f9[9], m[9], r, ux, uy, X, Y;
+            gather9(p, f, i, j, f9);
+            matvec9(T, f9, m);
+            orc_macro(p, f9, &r, &ux, &uy);
+            strain_rate_from(p, m, r, ux, uy, gx[q], gy[q], &X, &Y);
+            const double S = (m[5] - r * ux * uy) / (-r * s / p->omega[5]);
+            const double div = X + Y;
+            sxx[q] = r * (nu4 * (2 * X - div) + zeta * div);
+            syy[q] = r * (nu4 * (2 * Y - div) + zeta * div);
+            sxy[q] = r * nu5 * S;
+        }
+    free(rho);
+    free(gx);
+    free(gy);
+}
+
 void orc_moments(const orc_params *p, const double *f, double *rho, double *ux, double *uy)
 {
 #pragma omp parallel for schedule(static)

@@ -74,6 +74,7 @@ void orc_stream(const orc_params *p, const double *ft, double *f);
 void orc_step_node(const orc_params *p, const double *f, int i, int j, double *out9);
 void orc_run(const orc_params *p, double *f, double *work, long nsteps);
 void orc_moments(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
+void orc_stress(const orc_params *p, const double *f, double *sxx, double *syy, double *sxy);
 
 int orc_max_threads(void);
 void orc_set_threads(int n);
