@@ -141,6 +141,20 @@ int lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
  * NaN); LBM_E_DEVICE. */
 int lbm_residual(lbm_ctx *ctx, double *R);
 
+/* Local viscous stress at the current time level, computed in FP64 from the
+ * populations alone (no finite differences of the velocity): the strain
+ * rate d_x u_x, d_y u_y of Eq. 37-38 from the second-order non-equilibrium
+ * moments m_3, m_4 with the density-gradient terms of Eq. 40 (central
+ * differences, neighbours across walls or on solid nodes replaced by the node
+ * itself, as in the collision), the shear rate d_y u_x + d_x u_y from m_5
+ * (Eq. 39, no correction by Eq. 27), then the viscous stress of Eq. 30-31:
+ * sxx = rho [nu (2 d_x u_x - div u) + zeta div u], syy likewise,
+ * sxy = rho nu' (d_y u_x + d_x u_y), nu from omega_4, nu' from omega_5
+ * (Eq. 32), zeta from omega_3 (Eq. 33).  Host double[ny][nx] arrays; any
+ * pointer may be NULL; solid nodes get 0.  Synchronizes.
+ * Errors: LBM_E_INVAL (ctx NULL), LBM_E_NOMEM (staging buffer), LBM_E_DEVICE. */
+int lbm_stress(lbm_ctx *ctx, double *sxx, double *syy, double *sxy);
+
 /* FP64 totals over all fluid nodes at the current time level: out[0] = sum rho,
  * out[1] = sum rho ux, out[2] = sum rho uy (momentum including the F/2
  * shift).  Deterministic.  Synchronizes.  Errors: LBM_E_UNSTABLE (NaN/Inf),
@@ -164,6 +178,18 @@ int lbm_set_populations(lbm_ctx *ctx, const double *f);
  * copied; it takes effect for every later call.  Synchronizes.
  * Errors: LBM_E_NOMEM, LBM_E_DEVICE. */
 int lbm_set_mask(lbm_ctx *ctx, const unsigned char *mask);
+
+/* Replaces the uniform body force (Eq. 13) for the following steps and for
+ * the velocity definition rho u = sum f e + F/2 of later lbm_moments /
+ * lbm_sums / lbm_residual calls.  Errors: LBM_E_INVAL (not finite). */
+int lbm_set_force(lbm_ctx *ctx, double fx, double fy);
+
+/* Enqueues n steps, step i driven by the force (fx[i], fy[i]) (host arrays;
+ * fy may be NULL to keep the y component), as for a time-periodic force
+ * F_m cos(w t) (Sec. 5.3).  The last force stays set.  Returns without
+ * waiting.  Errors: LBM_E_INVAL (n < 0, fx NULL, a value not finite);
+ * LBM_E_DEVICE. */
+int lbm_step_forced(lbm_ctx *ctx, long n, const double *fx, const double *fy);
 
 /* Advances one step and replaces the state by the mean of the states before
  * and after that step.  A mode that flips sign every step (the staggered

@@ -443,6 +443,26 @@ extern "C" int lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy) {
     return LBM_OK;
 }
 
+extern "C" int lbm_stress(lbm_ctx *c, double *sxx, double *syy, double *sxy) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    const size_t n = static_cast<size_t>(c->nx) * c->ny;
+    int rc = ensure_stage(c, 4 * n * sizeof(double));
+    if (rc != LBM_OK) return rc;
+    double *d = c->d_stage;  // rho, then the three stress fields
+    const bool pull = c->form[c->cur] == kPost;
+    HIP_OR_FAIL(c, launch_moments(c->prec, pull, c->f[c->cur], d, d + n, d + 2 * n, c->G, c->Kd,
+                                  c->Kf, c->H, c->stream));
+    HIP_OR_FAIL(c, launch_stress(c->prec, pull, c->f[c->cur], d, d + n, d + 2 * n, d + 3 * n,
+                                 c->G, c->Kd, c->H, c->stream));
+    double *h[3] = {sxx, syy, sxy};
+    for (int i = 0; i < 3; ++i)
+        if (h[i])
+            HIP_OR_FAIL(c, hipMemcpyAsync(h[i], d + (i + 1) * n, n * sizeof(double),
+                                          hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
 static int fetch_result(lbm_ctx *c, double out[4]) {
     HIP_OR_FAIL(c, hipMemcpyAsync(out, c->d_partials + 4 * kMaxPartials, 4 * sizeof(double),
                                   hipMemcpyDeviceToHost, c->stream));
@@ -551,6 +571,42 @@ extern "C" int lbm_set_mask(lbm_ctx *c, const unsigned char *mask) {
     HIP_OR_FAIL(c, e2);
     c->G.mask = c->d_mask;
     c->G.tile_solid = c->d_tile_solid;
+    return LBM_OK;
+}
+
+static void apply_force(lbm_ctx *c, double fx, double fy) {
+    c->opts.force[0] = fx;
+    c->opts.force[1] = fy;
+    c->Kd.Fx = fx;
+    c->Kd.Fy = fy;
+    c->Kd.hFx = 0.5 * fx;
+    c->Kd.hFy = 0.5 * fy;
+    c->Kf.Fx = static_cast<float>(fx);
+    c->Kf.Fy = static_cast<float>(fy);
+    c->Kf.hFx = static_cast<float>(0.5 * fx);
+    c->Kf.hFy = static_cast<float>(0.5 * fy);
+    c->H.Fx = fx;
+    c->H.Fy = fy;
+}
+
+extern "C" int lbm_set_force(lbm_ctx *c, double fx, double fy) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!isfinite(fx) || !isfinite(fy)) return fail_ctx(c, LBM_E_INVAL, "force must be finite");
+    apply_force(c, fx, fy);
+    return LBM_OK;
+}
+
+extern "C" int lbm_step_forced(lbm_ctx *c, long n, const double *fx, const double *fy) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && !fx)) return fail_ctx(c, LBM_E_INVAL, "need n >= 0 and fx");
+    for (long i = 0; i < n; ++i)
+        if (!isfinite(fx[i]) || (fy && !isfinite(fy[i])))
+            return fail_ctx(c, LBM_E_INVAL, "force %ld is not finite", i);
+    for (long i = 0; i < n; ++i) {
+        apply_force(c, fx[i], fy ? fy[i] : c->opts.force[1]);
+        int rc = lbm_step(c, 1);  // the constants travel by value with each launch
+        if (rc != LBM_OK) return rc;
+    }
     return LBM_OK;
 }
 

@@ -146,6 +146,10 @@ hipError_t launch_average_states(int prec, bool pull_cur, const void *cur, bool 
 hipError_t launch_moments(int prec, bool pull, const void *src, double *rho, double *ux,
                           double *uy, const Geometry &G, const Consts<double> &Kd,
                           const Consts<float> &Kf, const HostSide &H, hipStream_t st);
+// local viscous stress from the state in src and its densities rho[ny][nx]
+hipError_t launch_stress(int prec, bool pull, const void *src, const double *rho, double *sxx,
+                         double *syy, double *sxy, const Geometry &G, const Consts<double> &Kd,
+                         const HostSide &H, hipStream_t st);
 // out[0..2] = sum rho, sum rho ux, sum rho uy, out[3] = 1 if NaN/Inf met
 hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, double *out,
                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,

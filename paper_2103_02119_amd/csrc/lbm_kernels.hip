@@ -847,6 +847,85 @@ __global__ void moments_kernel(const S *__restrict__ src, double *__restrict__ r
     }
 }
 
+// Density of the neighbour of (x, j) that the density gradient uses: across
+// a periodic face it wraps; across a wall, or onto a solid node, it is the
+// node's own density.
+__device__ __forceinline__ double nb_rho(const double *__restrict__ rho, const Geometry &G, int x,
+                                         int j, int dx, int dy) {
+    int xn = x + dx, jn = j + dy;
+    if (xn < 0) {
+        if (G.bc[kXmin] != kPeriodic) return rho[static_cast<long long>(j) * G.nx + x];
+        xn = G.nx - 1;
+    } else if (xn >= G.nx) {
+        if (G.bc[kXmax] != kPeriodic) return rho[static_cast<long long>(j) * G.nx + x];
+        xn = 0;
+    }
+    if (jn < 0) {
+        if (G.bc[kYmin] != kPeriodic) return rho[static_cast<long long>(j) * G.nx + x];
+        jn = G.ny - 1;
+    } else if (jn >= G.ny) {
+        if (G.bc[kYmax] != kPeriodic) return rho[static_cast<long long>(j) * G.nx + x];
+        jn = 0;
+    }
+    if (G.mask && G.mask[static_cast<long long>(jn) * G.pitch + xn])
+        return rho[static_cast<long long>(j) * G.nx + x];
+    return rho[static_cast<long long>(jn) * G.nx + xn];
+}
+
+// Local viscous stress of every node, in FP64, from its pre-collision
+// populations and the densities of its neighbours: the strain rate of
+// Eq. 37-39 (d_x u_x, d_y u_y from the second-order non-equilibrium moments
+// with the density-gradient terms of Eq. 40; the shear rate from m_5 alone,
+// its correction being zero by Eq. 27), then the viscous terms of Eq. 30-31
+// with nu and zeta of Eq. 32-33.  Solid nodes get 0.
+template <typename S, bool PULL>
+__global__ void stress_kernel(const S *__restrict__ src, const double *__restrict__ rho,
+                              double *__restrict__ sxx, double *__restrict__ syy,
+                              double *__restrict__ sxy, const Geometry G, const Consts<double> K,
+                              const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    const double nu4 = K.s * K.k4, zeta = K.s * K.k3, nu5 = K.s * (1.0 / K.w[5] - 0.5);
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) {
+            sxx[idx] = syy[idx] = sxy[idx] = 0.0;
+            continue;
+        }
+        double f9[9], r, ux, uy;
+        load_node<S, double, PULL>(src, G, K, row_info(j, G), col_info(x, G), f9);
+        macro_of(f9, H, r, ux, uy);
+        // raw second moments of the stored values (deviations from rho0 w_k
+        // when H.dev: the rest state's own m_3 = 2 cs2 rho0, m_4 = m_5 = 0)
+        double r00 = 0.0, r20 = 0.0, r02 = 0.0, r11 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            r00 += f9[k];
+            r20 += cx_of(k) * cx_of(k) * f9[k];
+            r02 += cy_of(k) * cy_of(k) * f9[k];
+            r11 += cx_of(k) * cy_of(k) * f9[k];
+        }
+        const double ux2 = ux * ux, uy2 = uy * uy;
+        const double Q3 = (r20 + K.a2 * r02) - 2.0 * K.s * r00 - r * (ux2 + uy2);
+        const double Q4 = (r20 - K.a2 * r02) - r * (ux2 - uy2);
+        const double N5 = K.a * r11 - r * ux * uy;
+        const double gx = 0.5 * (nb_rho(rho, G, x, j, 1, 0) - nb_rho(rho, G, x, j, -1, 0));
+        const double gy = K.half_inv_a * (nb_rho(rho, G, x, j, 0, 1) - nb_rho(rho, G, x, j, 0, -1));
+        const double tx = K.e1 * ux * gx, ty = K.e2 * uy * gy;
+        const double M3 = Q3 - tx - ty, M4 = Q4 - tx + ty;
+        const double b1 = K.b1c + 1.5 * ux2, b2 = K.b2c + 1.5 * uy2;
+        const double c1 = K.c1c + 1.5 * ux2, c2 = K.c2c - 1.5 * uy2;
+        const double idet = 1.0 / (r * (b1 * c2 - c1 * b2));
+        const double X = (c2 * M3 - b2 * M4) * idet;  // d ux / dx
+        const double Y = (b1 * M4 - c1 * M3) * idet;  // d uy / dy
+        const double shear = -N5 * K.w[5] / (r * K.s);  // d uy / dx + d ux / dy
+        const double div = X + Y;
+        sxx[idx] = r * (nu4 * (2.0 * X - div) + zeta * div);
+        syy[idx] = r * (nu4 * (2.0 * Y - div) + zeta * div);
+        sxy[idx] = r * nu5 * shear;
+    }
+}
+
 // ------------------------------------------------------------ reductions
 
 // Deterministic FP64 block sum of 4 values: wavefront shuffle tree, then
@@ -1106,6 +1185,22 @@ hipError_t launch_moments(int prec, bool pull, const void *src, double *rho, dou
         const double *s = static_cast<const double *>(src);
         if (pull) hipLaunchKernelGGL((moments_kernel<double, true>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
         else hipLaunchKernelGGL((moments_kernel<double, false>), grid, block, 0, st, s, rho, ux, uy, G, Kd, H);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stress(int prec, bool pull, const void *src, const double *rho, double *sxx,
+                         double *syy, double *sxy, const Geometry &G, const Consts<double> &Kd,
+                         const HostSide &H, hipStream_t st) {
+    const dim3 grid(conv_blocks(G)), block(256);
+    if (f32_storage(prec)) {
+        const float *s = static_cast<const float *>(src);
+        if (pull) hipLaunchKernelGGL((stress_kernel<float, true>), grid, block, 0, st, s, rho, sxx, syy, sxy, G, Kd, H);
+        else hipLaunchKernelGGL((stress_kernel<float, false>), grid, block, 0, st, s, rho, sxx, syy, sxy, G, Kd, H);
+    } else {
+        const double *s = static_cast<const double *>(src);
+        if (pull) hipLaunchKernelGGL((stress_kernel<double, true>), grid, block, 0, st, s, rho, sxx, syy, sxy, G, Kd, H);
+        else hipLaunchKernelGGL((stress_kernel<double, false>), grid, block, 0, st, s, rho, sxx, syy, sxy, G, Kd, H);
     }
     return hipGetLastError();
 }

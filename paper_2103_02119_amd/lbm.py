@@ -26,8 +26,9 @@ LBM_RC, LBM_RNR = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
-           "lbm_moments", "lbm_residual", "lbm_sums", "lbm_get_populations",
-           "lbm_set_populations", "lbm_set_mask", "lbm_set_rates", "lbm_smooth_step",
+           "lbm_moments", "lbm_stress", "lbm_residual", "lbm_sums", "lbm_get_populations",
+           "lbm_set_populations", "lbm_set_mask", "lbm_set_rates", "lbm_set_force",
+           "lbm_step_forced", "lbm_smooth_step",
            "lbm_steps_done",
            "lbm_launch_shape",
            "lbm_last_error", "lbm_destroy")
@@ -121,6 +122,7 @@ def load():
     L.lbm_set_fields.argtypes = [_CTX, _D, _D, _D]
     L.lbm_step.argtypes = [_CTX, ctypes.c_long]
     L.lbm_moments.argtypes = [_CTX, _D, _D, _D]
+    L.lbm_stress.argtypes = [_CTX, _D, _D, _D]
     L.lbm_residual.argtypes = [_CTX, _D]
     L.lbm_sums.argtypes = [_CTX, _D]
     L.lbm_get_populations.argtypes = [_CTX, _D]
@@ -130,6 +132,10 @@ def load():
     L.lbm_set_mask.restype = ctypes.c_int
     L.lbm_set_rates.argtypes = [_CTX, _D]
     L.lbm_set_rates.restype = ctypes.c_int
+    L.lbm_set_force.argtypes = [_CTX, ctypes.c_double, ctypes.c_double]
+    L.lbm_set_force.restype = ctypes.c_int
+    L.lbm_step_forced.argtypes = [_CTX, ctypes.c_long, _D, _D]
+    L.lbm_step_forced.restype = ctypes.c_int
     L.lbm_smooth_step.argtypes = [_CTX]
     L.lbm_smooth_step.restype = ctypes.c_int
     L.lbm_steps_done.argtypes = [_CTX]
@@ -140,7 +146,7 @@ def load():
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_destroy.argtypes = [_CTX]
     for name in ("lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step", "lbm_moments",
-                 "lbm_residual", "lbm_sums", "lbm_get_populations", "lbm_set_populations",
+                 "lbm_stress", "lbm_residual", "lbm_sums", "lbm_get_populations", "lbm_set_populations",
                  "lbm_launch_shape", "lbm_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _I = ctypes.POINTER(ctypes.c_int)
@@ -243,6 +249,13 @@ def lbm_moments(ctx, nx, ny):
     return rho, ux, uy
 
 
+def lbm_stress(ctx, nx, ny):
+    """(sxx, syy, sxy), each (ny, nx), of the current time level."""
+    out = tuple(np.empty((ny, nx)) for _ in range(3))
+    _check(load().lbm_stress(ctx, *(o.ctypes.data_as(_D) for o in out)), ctx)
+    return out
+
+
 def lbm_residual(ctx) -> float:
     R = ctypes.c_double()
     _check(load().lbm_residual(ctx, ctypes.byref(R)), ctx)
@@ -278,6 +291,19 @@ def _mask(mask, shape):
 def lbm_set_mask(ctx, nx, ny, mask=None):
     keep, p = _mask(mask, (ny, nx))
     _check(load().lbm_set_mask(ctx, p), ctx)
+
+
+def lbm_set_force(ctx, fx, fy=0.0):
+    _check(load().lbm_set_force(ctx, float(fx), float(fy)), ctx)
+
+
+def lbm_step_forced(ctx, fx, fy=None):
+    ax = np.ascontiguousarray(fx, dtype=np.float64)
+    ay = None if fy is None else np.ascontiguousarray(fy, dtype=np.float64)
+    if ay is not None and ay.shape != ax.shape:
+        raise ValueError("fx and fy must have the same length")
+    _check(load().lbm_step_forced(ctx, ax.size, ax.ctypes.data_as(_D),
+                                  None if ay is None else ay.ctypes.data_as(_D)), ctx)
 
 
 def lbm_smooth_step(ctx):
@@ -349,6 +375,9 @@ class Lattice:
     def moments(self):
         return lbm_moments(self.ctx, self.nx, self.ny)
 
+    def stress(self):
+        return lbm_stress(self.ctx, self.nx, self.ny)
+
     def residual(self):
         return lbm_residual(self.ctx)
 
@@ -372,6 +401,12 @@ class Lattice:
 
     def smooth_step(self):
         lbm_smooth_step(self.ctx)
+
+    def set_force(self, fx, fy=0.0):
+        lbm_set_force(self.ctx, fx, fy)
+
+    def step_forced(self, fx, fy=None):
+        lbm_step_forced(self.ctx, fx, fy)
 
     @property
     def steps_done(self):

@@ -1,0 +1,77 @@
+"""Parity of the local stress output (Eq. 37-40 with Eq. 30-33) with the
+oracle, on the state the GPU holds: lid-driven cavities (walls, a moving
+wall), a forced periodic channel, an obstacle, both collision models and the
+storage precisions.
+
+Tolerance: the stresses come from second moments of O(rho cs2) from which
+the equilibrium part is subtracted, so a rounding difference of a few ulp
+in those moments reaches the result as an absolute error of order
+eps * rho0 * cs2 whatever the size of the stress; the bound is
+1e-13 * rho0 * cs2 (about 500 ulp of that scale)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_02119_amd import lbm as L
+from paper_2103_02119_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(*args):
+    print("case:", *args, flush=True)
+
+
+def check(lat, p, cs2):
+    f = lat.get_populations()
+    ref = O.stress(p, f)
+    got = lat.stress()
+    scale = max(np.abs(r).max() for r in ref)
+    assert scale > 1e-9  # a flow with stress in it
+    for g, r in zip(got, ref):
+        assert np.abs(g - r).max() < 1e-13 * cs2, (np.abs(g - r).max(), scale)
+
+
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV, L.LBM_FP64_DEV])
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+def test_cavity_stress_matches_the_oracle(coll, prec):
+    announce("stress cavity", coll, prec)
+    nx, ny, a, tau, U = 67, 45, 0.5, 0.6, 0.05
+    cs2 = W.cavity_cs2(a)
+    rates = O.paper_rates(tau)
+    lat = L.Lattice(nx, ny, a, rates, bc_types=(1, 1, 1, 2), u_wall=((0, 0), (0, 0), (0, 0), (U, 0)),
+                    cs2=cs2, collision=coll, precision=prec)
+    p = O.make_params(nx, ny, a, cs2, rates, collision=O.RC if coll == L.LBM_RC else O.RNR,
+                      bc=(1, 1, 1, 2), u_wall=((0, 0), (0, 0), (0, 0), (U, 0)))
+    lat.step(301)
+    check(lat, p, cs2)
+    lat.step(1)  # the other ping-pong buffer / pull form
+    check(lat, p, cs2)
+    lat.close()
+
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+def test_forced_channel_with_an_obstacle(coll):
+    announce("stress channel + obstacle", coll)
+    nx, ny, a, tau, Fx = 130, 70, 0.25, 0.8, 2e-6
+    cs2 = 0.64 * a * a
+    rates = O.paper_rates(tau)
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[25:41, 40:52] = 1
+    lat = L.Lattice(nx, ny, a, rates, bc_types=(0, 0, 1, 1), cs2=cs2, collision=coll,
+                    force=(Fx, 0.0))
+    lat.set_mask(solid)
+    p = O.make_params(nx, ny, a, cs2, rates, force=(Fx, 0.0),
+                      collision=O.RC if coll == L.LBM_RC else O.RNR, bc=(0, 0, 1, 1), solid=solid)
+    lat.step(500)
+    check(lat, p, cs2)
+    sxx, syy, sxy = lat.stress()
+    assert (sxx[solid == 1] == 0).all() and (sxy[solid == 1] == 0).all()
+    lat.close()
+
+
+def test_null_outputs_are_skipped():
+    announce("stress null pointers")
+    lat = L.Lattice(64, 64, 1.0, O.paper_rates(0.8))
+    assert L.load().lbm_stress(lat.ctx, None, None, None) == 0
+    lat.close()
