@@ -537,7 +537,8 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
 
 def run_pipeline(n_train=3200, n_test=64, epochs=120, batch=16, seed=2103, test_seed=77,
                  out_dir=None, nx=256, ny=128, gen_max_steps=150_000, eval_max_steps=400_000,
-                 re_range=(100.0, 5000.0), log=_log_default):
+                 re_range=(100.0, 5000.0), gen_precision=L.LBM_FP32_DEV, gen_tol=2e-6,
+                 log=_log_default):
     """Generate steady fields with the batched solver, train the network on
     them, then compare cold and warm starts on unseen cases."""
     import json
@@ -548,6 +549,7 @@ def run_pipeline(n_train=3200, n_test=64, epochs=120, batch=16, seed=2103, test_
     t0 = time.perf_counter()
     params = I.warmstart_cases(n_train, seed=seed, re_range=re_range)
     X, (rho, ux, uy), masks, kept, gen_info = build_dataset(params, nx=nx, ny=ny,
+                                                            precision=gen_precision, tol=gen_tol,
                                                             max_steps=gen_max_steps, log=log)
     log(f"dataset: {gen_info}")
     from . import workloads as Wk
@@ -561,10 +563,14 @@ def run_pipeline(n_train=3200, n_test=64, epochs=120, batch=16, seed=2103, test_
                           val=(X[:nval], T[:nval], fluid[:nval]), log=log)
     test = I.warmstart_cases(n_test, seed=test_seed, re_range=re_range)
     cmp = warm_vs_cold(net, scales, test, nx=nx, ny=ny, max_steps=eval_max_steps, log=log)
+    # the validation error of predicting the rest state (all zeros), over the
+    # same whole batches that the validation loss covers
+    nv = (nval // batch) * batch
+    val_zero = float((T[:nv] ** 2 * fluid[:nv, ..., None]).sum() / max(int(fluid[:nv].sum()), 1))
     metrics = dict(dataset=gen_info, train_samples=int(len(X) - nval),
                    val_samples=int(nval), epochs=epochs, batch=batch,
                    train_seconds=round(t_train, 2), final_loss=hist[-1]["loss"],
-                   final_val=hist[-1].get("val"), warm_vs_cold=cmp,
+                   final_val=hist[-1].get("val"), val_zero_prediction=val_zero, warm_vs_cold=cmp,
                    total_seconds=round(time.perf_counter() - t0, 1))
     if out_dir:
         os.makedirs(out_dir, exist_ok=True)

@@ -1,0 +1,58 @@
+"""Stability margins (Sec. 6) on the GPU, reduced in size: the bisection on
+the lid speed agrees with the same bisection run on the CPU oracle, and the
+central-moment collision sustains at least the raw-moment one's lid speed
+(Fig. 17) and a higher Reynolds number (Table 6)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2103_02119_amd import lbm as L
+from paper_2103_02119_amd import stability as S
+from paper_2103_02119_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(*args):
+    print("case:", *args, flush=True)
+
+
+def oracle_survives(nx, ny, a, tau, U, coll, steps, check_every=1000):
+    cs2 = W.cavity_cs2(a)
+    p = O.make_params(nx, ny, a, cs2, O.paper_rates(tau), collision=coll, bc=(1, 1, 1, 2),
+                      u_wall=((0, 0), (0, 0), (0, 0), (U, 0)))
+    f = O.init(p)
+    for _ in range(steps // check_every):
+        f = O.run(p, f, check_every)
+        if not np.isfinite(f).all():
+            return False
+    return True
+
+
+def test_lid_speed_bisection_matches_the_oracle_and_rc_is_at_least_as_stable():
+    announce("lid speed thresholds")
+    grid = (21, 41, 0.5)
+    res = S.max_lid_velocity((0.52, 0.6), grids=(grid,), steps=100_000, rounds=6, u_max=0.6)
+    by = {(r["tau"], r["collision"]): r for r in res}
+    for tau in (0.52, 0.6):
+        assert by[(tau, "RC")]["stable_U"] >= by[(tau, "RNR")]["stable_U"], by
+    # the same bisection on the oracle for one combination
+    lo, hi = 0.0, 0.6
+    if oracle_survives(*grid, 0.52, hi, O.RC, 100_000):
+        lo = hi
+    for _ in range(5):
+        if lo == hi:
+            break
+        mid = 0.5 * (lo + hi)
+        if oracle_survives(*grid, 0.52, mid, O.RC, 100_000):
+            lo = mid
+        else:
+            hi = mid
+    assert by[(0.52, "RC")]["stable_U"] == pytest.approx(lo, abs=1e-12)
+
+
+def test_table6_rc_sustains_a_higher_reynolds_number():
+    announce("table 6, 100 x 200")
+    res = S.max_reynolds(grids=((100, 200),), steps=100_000, rounds=7, re_lo=1000.0, re_hi=30000.0)
+    by = {r["collision"]: r for r in res}
+    assert by["RC"]["stable_Re"] > by["RNR"]["stable_Re"], res
