@@ -164,9 +164,15 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, ui
 // direction is a wavefront-uniform scalar offset, the column shift an
 // immediate, so the only per-lane address is one 32-bit byte offset per row.
 // Needs the whole buffer below 4 GiB (Geometry::buf_ok).
-template <typename S, typename R, bool PULL>
+// XW = 1 / 2: the tile's first / last column lies on a wall face (x = 0 /
+// x = nx - 1, not periodic), rows interior.  The lane on the wall (wlane)
+// takes the half-way bounce-back of Eq. 57-59 for the three links that
+// would come from outside, from three extra loads of its own node's
+// opposite planes; every other lane is interior.
+template <typename S, typename R, bool PULL, int XW = 0>
 __device__ __forceinline__ void load_interior(const S *__restrict__ src, const Geometry &G,
-                                              int j, int x, R (&f)[9]) {
+                                              int j, int x, R (&f)[9],
+                                              const Consts<R> *K = nullptr, bool wlane = false) {
     constexpr uint32_t B = sizeof(S);
     const uint32_t pb = static_cast<uint32_t>(G.plane) * B;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, 9u * pb);
@@ -178,6 +184,14 @@ __device__ __forceinline__ void load_interior(const S *__restrict__ src, const G
         const uint32_t soff = static_cast<uint32_t>(k) * pb -
                               static_cast<uint32_t>(cy * G.pitch) * B;
         f[k] = static_cast<R>(buf_load(static_cast<S *>(nullptr), rs, obm + (1 - cx) * B, soff));
+        if constexpr (PULL && XW != 0) {
+            if (cx == (XW == 1 ? 1 : -1)) {
+                const int face = XW == 1 ? kXmin : kXmax;
+                const R bb = static_cast<R>(buf_load(static_cast<S *>(nullptr), rs, obm + B,
+                                                     static_cast<uint32_t>(opp_of(k)) * pb));
+                f[k] = wlane ? bb - K->dwall[face][k] : f[k];
+            }
+        }
     }
 }
 
@@ -449,18 +463,21 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
 // so it carries no boundary logic and no wall constants.  The halo columns'
 // populations arrive with the prologue and are summed only afterwards, so
 // the tile starts with a single latency round.
-template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU, bool GENERIC>
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU, bool GENERIC, int XW = 0>
 __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__ dst,
                                       const Geometry &G, const Consts<R> &K, int lane, int j0,
                                       int j1, int x0, int x, int xraw, int xlast, bool active,
                                       bool wall_left, bool wall_right) {
     constexpr int D = sizeof(R) == 4 ? 3 : 2;
     const ColInfo c = col_info(x, G);
+    // the lane whose outer neighbour is the wall (XW tiles); lanes past
+    // nx - 1 repeat column nx - 1 and are not stored
+    const bool wlane = XW == 1 ? (x == 0) : (XW == 2 ? (x == G.nx - 1) : false);
     auto load_row = [&](int jj, R (&f9)[9]) {
         if (GENERIC)
             load_node<S, R, PULL>(src, G, K, row_info(jj, G), c, f9);
         else
-            load_interior<S, R, PULL>(src, G, jj, x, f9);
+            load_interior<S, R, PULL, XW>(src, G, jj, x, f9, &K, wlane);
     };
     // a row index that exists (wrapping periodically) or -1 beyond a wall
     auto row_of = [&](int jj) -> int {
@@ -589,12 +606,22 @@ __device__ __forceinline__ void run_tile(const S *__restrict__ src, S *__restric
     const bool wall_left = (x0 == 0) && G.bc[kXmin] != kPeriodic;
     const bool wall_right = (xlast == G.nx - 1) && G.bc[kXmax] != kPeriodic;
     // every pulled node (rows j0-1 .. j1, columns x0-1 .. x0+64) interior
-    // and fluid?
-    const bool interior = G.buf_ok && !near_solid && (x0 > 0) && (x0 + kWave < G.nx) &&
-                          (j0 >= 2) && (j1 <= G.ny - 2);
-    if (interior)
+    // and fluid, or outside only across one x wall?
+    const bool rows_in = G.buf_ok && !near_solid && (j0 >= 2) && (j1 <= G.ny - 2);
+    const bool cols_in = (x0 > 0) && (x0 + kWave < G.nx);
+    // (the wall-column variants only for the paper's omega_6..8 = 1, whose
+    // collision is small enough for the extra registers)
+    if (rows_in && cols_in)
         march<S, R, DEV, COLL, PULL, HU, false>(src, dst, G, K, lane, j0, j1, x0, x, xraw, xlast,
                                                  active, wall_left, wall_right);
+    else if (HU && rows_in && wall_left && x0 + kWave < G.nx)
+        march<S, R, DEV, COLL, PULL, HU, false, HU ? 1 : 0>(src, dst, G, K, lane, j0, j1, x0, x,
+                                                             xraw, xlast, active, wall_left,
+                                                             wall_right);
+    else if (HU && rows_in && wall_right && x0 > 0)
+        march<S, R, DEV, COLL, PULL, HU, false, HU ? 2 : 0>(src, dst, G, K, lane, j0, j1, x0, x,
+                                                             xraw, xlast, active, wall_left,
+                                                             wall_right);
     else
         march<S, R, DEV, COLL, PULL, HU, true>(src, dst, G, K, lane, j0, j1, x0, x, xraw, xlast,
                                                 active, wall_left, wall_right);

@@ -161,6 +161,67 @@ def shear_layer(nx=2048, ny=8192, a=0.25, nu=1e-4, u0=0.04, kappa=80.0, delta=0.
                 **out)
 
 
+def shear_layer_sweep(nus=(1e-4, 2e-4, 4e-4, 8e-4, 1.6e-3), steps=20_000, check_every=100,
+                      log=None, **kw):
+    """Blow-up steps of both collision models and both storage precisions on
+    the shear layer over a range of viscosities (tau = nu / cs2 + 1/2)."""
+    out = []
+    for nu in nus:
+        r = shear_layer(nu=nu, steps=steps, check_every=check_every,
+                        compare_every=max(check_every, steps // 4), log=log, **kw)
+        out.append(dict(nu=nu, tau=r["tau"],
+                        **{f"{c}_{p}": r[c][f"blowup_step_{p}"] for c in ("RC", "RNR")
+                           for p in ("fp64", "fp32")}))
+    return out
+
+
+def _shear_survives(nx, ny, a, nu, cs2, coll, precision, steps, check_every, fields):
+    tau = nu / cs2 + 0.5
+    rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
+    lat = L.Lattice(nx, ny, a, rates, cs2=cs2, collision=coll, precision=precision)
+    lat.set_fields(*fields)
+    ok = True
+    for _ in range(steps // check_every):
+        lat.step(check_every)
+        try:
+            lat.sums()
+        except L.LbmError as e:
+            if e.code != L.LBM_E_UNSTABLE:
+                raise
+            ok = False
+            break
+    lat.close()
+    return ok
+
+
+def shear_layer_margin(nx=2048, ny=8192, a=0.25, cs2=0.04, u0=0.04, kappa=80.0, delta=0.05,
+                       nu_lo=1e-4, nu_hi=2e-2, rounds=6, steps=20_000, check_every=1000,
+                       precision=L.LBM_FP64, log=None):
+    """Smallest viscosity at which the shear layer stays finite for `steps`
+    steps, per collision model: bisection on log nu (the stable end of the
+    final bracket is reported)."""
+    from . import inputs as I
+
+    fields = I.shear_layer(nx, ny, a, u0=u0, kappa=kappa, delta=delta)
+    out = {}
+    for coll in (L.LBM_RC, L.LBM_RNR):
+        name = "RC" if coll == L.LBM_RC else "RNR"
+        lo, hi = np.log(nu_lo), np.log(nu_hi)
+        for r in range(rounds):
+            mid = 0.5 * (lo + hi)
+            if _shear_survives(nx, ny, a, float(np.exp(mid)), cs2, coll, precision, steps,
+                               check_every, fields):
+                hi = mid
+            else:
+                lo = mid
+            if log:
+                log(f"shear margin {name}: round {r + 1}/{rounds}, bracket "
+                    f"[{np.exp(lo):.3g}, {np.exp(hi):.3g}]")
+        out[name] = dict(min_stable_nu=float(np.exp(hi)), max_unstable_nu=float(np.exp(lo)),
+                         tau_at_min_stable=float(np.exp(hi) / cs2 + 0.5))
+    return dict(nx=nx, ny=ny, a=a, cs2=cs2, steps=steps, precision=precision, **out)
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -177,7 +238,12 @@ if __name__ == "__main__":
     if args.study in ("reynolds", "all"):
         res["max_reynolds"] = max_reynolds(log=log)
     if args.study in ("shear", "all"):
-        res["shear_layer"] = shear_layer(log=log)
+        # the configured viscosity, with the blow-up step resolved to 50 steps
+        res["shear_layer"] = shear_layer(steps=5000, check_every=50, compare_every=100, log=log)
+        res["shear_layer_margin"] = shear_layer_margin(log=log)
+        # above both models' limits: FP32 storage against FP64 over 50 000 steps
+        res["shear_layer_fp32"] = shear_layer(nu=6e-3, steps=50_000, check_every=1000,
+                                              compare_every=5000, log=log)
     text = json.dumps(res)
     print(text, flush=True)
     if args.out:
