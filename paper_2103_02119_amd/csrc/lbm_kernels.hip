@@ -490,11 +490,22 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
 #pragma unroll
     for (int k = 0; k < 9; ++k) hfl[k] = hfr[k] = R(0);
     {
-        const RowInfo rh = row_info(min(j0 + lane, j1 - 1), G);
-        if (!wall_left)
-            load_node<S, R, PULL>(src, G, K, rh, col_info(x0 > 0 ? x0 - 1 : G.nx - 1, G), hfl);
-        if (!wall_right)
-            load_node<S, R, PULL>(src, G, K, rh, col_info(xlast < G.nx - 1 ? xlast + 1 : 0, G), hfr);
+        const int jh = min(j0 + lane, j1 - 1);
+        const RowInfo rh = row_info(jh, G);
+        // off the generic path the halo columns' own pulls stay inside the
+        // lattice unless the right halo is the last column: buffer loads then
+        if (!wall_left) {
+            if (!GENERIC)
+                load_interior<S, R, PULL>(src, G, jh, x0 - 1, hfl);
+            else
+                load_node<S, R, PULL>(src, G, K, rh, col_info(x0 > 0 ? x0 - 1 : G.nx - 1, G), hfl);
+        }
+        if (!wall_right) {
+            if (!GENERIC && xlast + 2 < G.nx)
+                load_interior<S, R, PULL>(src, G, jh, xlast + 1, hfr);
+            else
+                load_node<S, R, PULL>(src, G, K, rh, col_info(xlast < G.nx - 1 ? xlast + 1 : 0, G), hfr);
+        }
     }
     // prologue: the ring row below and rows j0 .. j0 + D - 1
     const bool below = !GENERIC || (j0 > 0) || G.bc[kYmin] == kPeriodic;
