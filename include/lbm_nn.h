@@ -3,7 +3,7 @@
  * library, liblbm.so): a convolutional encoder-decoder that maps an obstacle
  * mask and the flow parameters (Re, a) to a steady (rho, u, v) field, from
  * which the lattice of include/lbm.h starts (lbm_set_fields) instead of from
- * rest.  The lattice Boltzmann solver stays the judge of the result: the
+ * rest.  The lattice Boltzmann solver alone decides the result: the
  * network only chooses the initial state.
  *
  * Conventions

@@ -103,7 +103,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
-                           "(python -c 'import __graft_entry__ as g; g.build()')")
+                           "(python -m paper_2103_02119_amd.build)")
     # PyTorch-ROCm ships its own HIP and HSA runtimes.  Load them first, so
     # that the library binds to the runtime already in the process: if the
     # system runtime came first, torch's own would later fail to open the GPU.

@@ -480,8 +480,8 @@ SETTLE_STEPS = 50   # steps before the smoothing step of a start from fields
 
 def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_every=1000,
                  max_steps=400_000, log=_log_default):
-    """Steps and wall time to a per-step residual of tol (FP64, the plain
-    lattice Boltzmann scheme as judge) for the same cases started
+    """Steps and wall time to a per-step residual of tol (FP64; the plain
+    lattice Boltzmann scheme decides convergence) for the same cases started
       cold        from rest,
       cold+smooth from rest, with one smoothing step after SETTLE_STEPS,
       warm        from the network's prediction (lbm_set_fields),

@@ -1,6 +1,6 @@
 """The learned warm start end to end on small cavities (64 x 32 nodes):
 steady fields from the batched solver, training on the GPU kernels, and the
-plain lattice Boltzmann scheme as the judge of the result.
+plain lattice Boltzmann scheme deciding convergence.
 
 At this size the cavities converge from rest within a few ten thousand
 steps once the smoothing step has removed the impulsive start's staggered
