@@ -100,3 +100,26 @@ def test_shallow_cavity_rectangular_lattice_matches_the_square_one():
     assert res["square"]["steps"] and res["rectangular"]["steps"]
     assert res["node_ratio"] == pytest.approx(3.2)
     assert res["max_abs_diff_u_vertical"] < 1e-2 and res["max_abs_diff_v_horizontal"] < 5e-2
+
+
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+def test_taylor_green_decay_at_full_size(prec):
+    """1024 x 2048 nodes at a = 0.5 (a square physical box of side 1024),
+    u0 = 0.02, nu = 0.1 (tau = 1.125 at cs2 = 0.16): after step 1000 the
+    velocity amplitude decays at 2 nu k^2 within 1% (RC)."""
+    from paper_2103_02119_amd import inputs as I
+
+    announce("taylor-green 1024x2048", prec)
+    nx, ny, a, cs2, nu, u0 = 1024, 2048, 0.5, 0.16, 0.1, 0.02
+    tau = nu / cs2 + 0.5
+    lat = L.Lattice(nx, ny, a, O.paper_rates(tau), cs2=cs2, precision=prec)
+    lat.set_fields(*I.taylor_green(nx, ny, a, u0, cs2))
+    lat.step(1000)
+    _, ux0, _ = lat.moments()
+    lat.step(19_000)
+    _, ux1, _ = lat.moments()
+    k = 2 * np.pi / nx
+    rate = np.log(np.abs(ux0).max() / np.abs(ux1).max()) / 19_000
+    print("decay rate / 2 nu k^2 =", rate / (2 * nu * k * k), flush=True)
+    assert abs(rate / (2 * nu * k * k) - 1) < 1e-2
+    lat.close()
