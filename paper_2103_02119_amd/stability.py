@@ -227,7 +227,7 @@ if __name__ == "__main__":
     import json
 
     ap = argparse.ArgumentParser(description="stability margins of RC-LBM and RNR-LBM")
-    ap.add_argument("--study", choices=["lid", "reynolds", "shear", "all"], default="all")
+    ap.add_argument("--study", choices=["lid", "reynolds", "shear", "margin", "all"], default="all")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     log = lambda s: print(s, flush=True)  # noqa: E731
@@ -244,6 +244,11 @@ if __name__ == "__main__":
         # above both models' limits: FP32 storage against FP64 over 50 000 steps
         res["shear_layer_fp32"] = shear_layer(nu=6e-3, steps=50_000, check_every=1000,
                                               compare_every=5000, log=log)
+    if args.study == "margin":
+        # the shear layer's viscosity margin over its full 50 000 steps, both precisions
+        res["shear_layer_margin_50k"] = [
+            shear_layer_margin(nu_lo=1e-3, nu_hi=2e-2, rounds=5, steps=50_000, precision=p, log=log)
+            for p in (L.LBM_FP64, L.LBM_FP32_DEV)]
     text = json.dumps(res)
     print(text, flush=True)
     if args.out:
