@@ -188,3 +188,30 @@ def test_batch_default_opts():
     o = L.lbm_batch_default_opts()
     assert o.collision == L.LBM_RC and o.precision == L.LBM_FP64 and o.corrections == 1
     assert o.rows_per_wave == 0 and o.workgroups == 0 and o.graph_steps == 0 and o.stream is None
+
+
+def test_null_handles_are_rejected_before_touching_the_device():
+    lib = L.load()
+    D = ctypes.POINTER(ctypes.c_double)
+    d = (ctypes.c_double * 9)()
+    pd = ctypes.cast(d, D)
+    calls = {
+        "lbm_set_fields": (None, None, None, None),
+        "lbm_step": (None, 1),
+        "lbm_moments": (None, None, None, None),
+        "lbm_stress": (None, None, None, None),
+        "lbm_sums": (None, pd),
+        "lbm_residual": (None, pd),
+        "lbm_get_populations": (None, pd),
+        "lbm_set_populations": (None, pd),
+        "lbm_set_mask": (None, None),
+        "lbm_set_rates": (None, pd),
+        "lbm_set_force": (None, 0.0, 0.0),
+        "lbm_step_forced": (None, 1, pd, pd),
+        "lbm_smooth_step": (None,),
+    }
+    for name, args in calls.items():
+        assert getattr(lib, name)(*args) == L.LBM_E_INVAL, name
+    assert lib.lbm_destroy(None) == L.LBM_OK
+    assert lib.lbm_batch_step(None, 1) == L.LBM_E_INVAL
+    assert lib.lbm_batch_destroy(None) == L.LBM_OK
