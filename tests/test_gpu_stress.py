@@ -75,3 +75,22 @@ def test_null_outputs_are_skipped():
     lat = L.Lattice(64, 64, 1.0, O.paper_rates(0.8))
     assert L.load().lbm_stress(lat.ctx, None, None, None) == 0
     lat.close()
+
+
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+def test_sound_wave_with_bulk_viscosity(coll):
+    """omega_3 != omega_4 (zeta != nu), periodic, a = 0.5: the bulk term of
+    the normal stresses against the oracle."""
+    announce("stress sound wave", coll)
+    nx, ny, a = 128, 16, 0.5
+    cs2 = 0.16
+    rates = O.paper_rates(0.8)
+    rates[3] = 1 / 0.6
+    ux = np.tile(1e-3 * np.sin(2 * np.pi * np.arange(nx) / nx), (ny, 1))
+    rho = 1 + ux / np.sqrt(cs2)
+    lat = L.Lattice(nx, ny, a, rates, cs2=cs2, collision=coll)
+    lat.set_fields(rho, ux, np.zeros((ny, nx)))
+    p = O.make_params(nx, ny, a, cs2, rates, collision=O.RC if coll == L.LBM_RC else O.RNR)
+    lat.step(200)
+    check(lat, p, cs2)
+    lat.close()
