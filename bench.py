@@ -396,7 +396,7 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_over_algorithmic": traffic_ratio,
             "algorithmic_bytes_per_launch": bytes_per_lu * nodes,
-            "kernel": "lbm::step_kernel",
+            "kernel": "lbm::tile_step_kernel" if args.rows == 0 else "lbm::step_kernel",
             "bytes_per_lu": bytes_per_lu,
             "kernel_us": round(1e3 * kern_ms, 3),
         },

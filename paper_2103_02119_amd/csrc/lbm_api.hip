@@ -255,6 +255,11 @@ static void choose_launch(lbm_ctx *c) {
     const int rows = c->opts.rows_per_wave > 0 ? c->opts.rows_per_wave : auto_rows(nodes, c->prec);
     set_rows(G, rows);
     G.nt_store = 2.0 * static_cast<double>(c->f_bytes) > 512.0 * 1024 * 1024 ? 1 : 0;
+    // an explicit rows-per-wavefront choice selects the march; otherwise the
+    // tile kernel, with taller tiles once the buffers exceed the Infinity
+    // Cache (measured: 8 rows best on the 512 x 1024 cavity, 16 on the
+    // 2048 x 8192 lattice)
+    G.tile_rows = c->opts.rows_per_wave > 0 ? 0 : (G.nt_store ? 16 : 8);
 }
 
 int lbm::validate_case(int nx, int ny, double r, const double *rates, const lbm_bc *bc,
@@ -654,8 +659,9 @@ extern "C" long lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : 0; }
 
 extern "C" int lbm_launch_shape(const lbm_ctx *c, int *rows_per_wave, int *workgroups) {
     if (!c) return LBM_E_INVAL;
-    if (rows_per_wave) *rows_per_wave = c->G.rows;
-    if (workgroups) *workgroups = c->G.nblocks;
+    const bool tile = uses_tile_kernel(c->G);
+    if (rows_per_wave) *rows_per_wave = tile ? c->G.tile_rows : c->G.rows;
+    if (workgroups) *workgroups = tile ? tile_workgroups(c->G) : c->G.nblocks;
     return LBM_OK;
 }
 

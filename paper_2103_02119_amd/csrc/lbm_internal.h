@@ -49,6 +49,8 @@ struct Geometry {
     int corr;                // 1: Eq. 23-27 corrections on
     int buf_ok;              // 1: a population buffer is below 4 GiB (buffer addressing)
     int nt_store;            // 1: non-temporal population stores (buffers exceed the MALL)
+    int tile_rows;           // > 0: the one-node-per-thread tile kernel with tiles of 64 x
+                             // tile_rows (taken when no obstacle mask is set); 0: the march
     long long plane;         // pitch * ny
     const unsigned char *mask;        // obstacle mask [ny][pitch], nonzero = solid (or null)
     const unsigned char *tile_solid;  // per step-kernel tile: a solid node in its neighbourhood
@@ -128,6 +130,10 @@ const char *create_error_text();
 int set_create_error(const char *msg);
 
 // ---- launchers implemented in lbm_kernels.hip (return hipError_t) ----
+// workgroups of the tile kernel for a lattice (whole groups of 8)
+int tile_workgroups(const Geometry &G);
+// the step kernel a launch takes: the tile kernel unless tile_rows is 0 or a mask is set
+inline bool uses_tile_kernel(const Geometry &G) { return G.tile_rows > 0 && !G.mask; }
 hipError_t launch_step(int prec, int coll, bool pull, bool higher_unit, const void *src, void *dst,
                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
                        hipStream_t st);

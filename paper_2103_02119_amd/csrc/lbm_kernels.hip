@@ -732,12 +732,152 @@ hipError_t launch_batch_step(int prec, int coll, bool hu, void *b0, void *b1,
     }
 }
 
+// ------------------------------------------------------------ tile kernel
+
+// Neighbour column / row of the density gradient: wrapped across a periodic
+// face, -1 across a wall.
+__device__ __forceinline__ int nb_col(int x, int d, const Geometry &G) {
+    const int n = x + d;
+    if (n < 0) return G.bc[kXmin] == kPeriodic ? G.nx - 1 : -1;
+    if (n >= G.nx) return G.bc[kXmax] == kPeriodic ? 0 : -1;
+    return n;
+}
+__device__ __forceinline__ int nb_row(int j, int d, const Geometry &G) {
+    const int n = j + d;
+    if (n < 0) return G.bc[kYmin] == kPeriodic ? G.ny - 1 : -1;
+    if (n >= G.ny) return G.bc[kYmax] == kPeriodic ? 0 : -1;
+    return n;
+}
+
+// One node per thread: a workgroup of TY wavefronts owns a tile of 64
+// columns x TY rows.  Every thread pulls its node's populations and puts the
+// node's density in an LDS tile; the densities of the one-node ring around
+// the tile come from extra pulls by three of the wavefronts (the row below,
+// the row above, the two columns).  After one barrier each thread forms the
+// density gradient from LDS and collides.  Unlike the march there is no
+// serial dependence between rows, so every load of the tile is in flight at
+// once: the shape for lattices that fit the Infinity Cache.
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU, int TY>
+__global__ void __launch_bounds__(kWave * TY)
+tile_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
+                 const Consts<R> K, int ntx, int nty) {
+    __shared__ R srho[TY + 2][kWave + 2];
+    const int tx = threadIdx.x & (kWave - 1);
+    const int ty = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    int b = blockIdx.x;
+    const int nb = static_cast<int>(gridDim.x);
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
+    if (b >= ntx * nty) return;                             // padding workgroup (whole block)
+    const int x0 = (b % ntx) * kWave, j0 = (b / ntx) * TY;
+    const int nact = min(kWave, G.nx - x0), nrow = min(TY, G.ny - j0);
+    const int tc = min(tx, nact - 1), tr = min(ty, nrow - 1);
+    const int x = x0 + tc, j = j0 + tr;
+    const bool active = tx < nact && ty < nrow;
+    // every node pulled by the tile or its density ring interior, no mask:
+    // buffer loads without boundary logic
+    const bool fast = G.buf_ok && !G.mask && x0 >= 2 && x0 + nact + 1 < G.nx && j0 >= 2 &&
+                      j0 + nrow + 1 < G.ny;
+    auto load = [&](int xx, int jj, R (&f)[9]) {
+        if (fast)
+            load_interior<S, R, PULL>(src, G, jj, xx, f);
+        else
+            load_node<S, R, PULL>(src, G, K, row_info(jj, G), col_info(xx, G), f);
+    };
+    R f[9];
+    load(x, j, f);
+    // the density ring
+    const int jb = nb_row(j0, -1, G), jt = nb_row(j0 + nrow - 1, 1, G);
+    const int xl = nb_col(x0, -1, G), xr = nb_col(x0 + nact - 1, 1, G);
+    R hb = R(0), ht = R(0), hc = R(0);
+    if (ty == 0 && jb >= 0) {
+        R h[9];
+        load(x, jb, h);
+        hb = sum9(h);
+    }
+    if (ty == nrow - 1 && jt >= 0) {
+        R h[9];
+        load(x, jt, h);
+        ht = sum9(h);
+    }
+    // lanes 0 .. nrow-1: column xl, lanes 32 .. 32+nrow-1: column xr
+    const int cw = nrow > 1 ? 1 : 0;
+    const int hrow = j0 + (tx & 31);
+    const bool hlane = ty == cw && (tx & 31) < nrow && ((tx < 32) ? xl >= 0 : xr >= 0);
+    if (hlane) {
+        R h[9];
+        load(tx < 32 ? xl : xr, hrow, h);
+        hc = sum9(h);
+    }
+    const R rc = sum9(f);
+    srho[tr + 1][tc + 1] = rc;
+    if (ty == 0 && jb >= 0) srho[0][tc + 1] = hb;
+    if (ty == nrow - 1 && jt >= 0) srho[nrow + 1][tc + 1] = ht;
+    if (hlane) srho[(tx & 31) + 1][tx < 32 ? 0 : nact + 1] = hc;
+    __syncthreads();
+
+    // neighbours' densities; across a wall, or on a solid node, the node's own
+    const int nxl = nb_col(x, -1, G), nxr = nb_col(x, 1, G);
+    const int nyb = nb_row(j, -1, G), nyt = nb_row(j, 1, G);
+    R rl = nxl < 0 ? rc : srho[tr + 1][tc];
+    R rgt = nxr < 0 ? rc : srho[tr + 1][tc + 2];
+    R rbu = nyb < 0 ? rc : srho[tr][tc + 1];
+    R rnu = nyt < 0 ? rc : srho[tr + 2][tc + 1];
+    bool solid = false;
+    if (G.mask) {
+        const unsigned char *m = G.mask;
+        solid = m[static_cast<long long>(j) * G.pitch + x] != 0;
+        if (nxl >= 0 && m[static_cast<long long>(j) * G.pitch + nxl]) rl = rc;
+        if (nxr >= 0 && m[static_cast<long long>(j) * G.pitch + nxr]) rgt = rc;
+        if (nyb >= 0 && m[static_cast<long long>(nyb) * G.pitch + x]) rbu = rc;
+        if (nyt >= 0 && m[static_cast<long long>(nyt) * G.pitch + x]) rnu = rc;
+    }
+    const R gx = (rgt - rl) * R(0.5);
+    const R gy = (rnu - rbu) * K.half_inv_a;
+    const Pre<R> q = collide_pre<R, DEV, COLL>(f, K);
+    R out[9];
+    collide_post<R, DEV, COLL, HU>(f, q, gx, gy, G.corr, K, out);
+    if (solid) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[k] = K.rest[k];
+    }
+    if (active) store_node(dst, G, j, x, out);
+}
+
+int tile_workgroups(const Geometry &G) {
+    const int ty = G.tile_rows == 16 ? 16 : 8;
+    const int n = ((G.nx + kWave - 1) / kWave) * ((G.ny + ty - 1) / ty);
+    return (n + 7) / 8 * 8;
+}
+
 template <typename S, typename R, bool DEV>
 static hipError_t step_dispatch(int coll, bool pull, bool hu, const void *src, void *dst,
                                 const Geometry &G, const Consts<R> &K, hipStream_t st) {
     const dim3 grid(G.nblocks), block(kBlock);
     const S *s = static_cast<const S *>(src);
     S *d = static_cast<S *>(dst);
+    if (uses_tile_kernel(G)) {
+        const int ntx = (G.nx + kWave - 1) / kWave, ty = G.tile_rows == 16 ? 16 : 8;
+        const int nty = (G.ny + ty - 1) / ty;
+        const dim3 tgrid(tile_workgroups(G)), tblock(kWave * ty);
+#define LBM_TSTEP(C, P, H)                                                                        \
+    do {                                                                                          \
+        if (ty == 16)                                                                             \
+            hipLaunchKernelGGL((tile_step_kernel<S, R, DEV, C, P, H, 16>), tgrid, tblock, 0, st, s, \
+                               d, G, K, ntx, nty);                                                \
+        else                                                                                      \
+            hipLaunchKernelGGL((tile_step_kernel<S, R, DEV, C, P, H, 8>), tgrid, tblock, 0, st, s,  \
+                               d, G, K, ntx, nty);                                                \
+    } while (0)
+        if (coll == kRC) {
+            if (pull) { if (hu) LBM_TSTEP(kRC, true, true); else LBM_TSTEP(kRC, true, false); }
+            else { if (hu) LBM_TSTEP(kRC, false, true); else LBM_TSTEP(kRC, false, false); }
+        } else {
+            if (pull) { if (hu) LBM_TSTEP(kRNR, true, true); else LBM_TSTEP(kRNR, true, false); }
+            else { if (hu) LBM_TSTEP(kRNR, false, true); else LBM_TSTEP(kRNR, false, false); }
+        }
+#undef LBM_TSTEP
+        return hipGetLastError();
+    }
 #define LBM_STEP(C, P, H) \
     hipLaunchKernelGGL((step_kernel<S, R, DEV, C, P, H>), grid, block, 0, st, s, d, G, K)
     // the two-row kernel pays off with FP32 arithmetic only (measured: 13.5 vs

@@ -113,16 +113,17 @@ def test_degenerate_shapes(name, shape):
 @pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
 @pytest.mark.parametrize("name", ["periodic", "cavity"])
 def test_results_do_not_depend_on_the_launch_shape(name, prec):
-    """Bit-identical results for every rows-per-wavefront choice (which
-    moves tiles between the interior and the generic code paths)."""
+    """Bit-identical results for the tile kernel (rows 0: automatic) and for
+    every rows-per-wavefront choice of the march (which moves tiles between
+    the interior and the generic code paths)."""
     nx, ny = 150, 70
     p, _ = make(name, nx, ny)
     f0 = random_state(p, seed=3)
     outs = []
-    for rows in (1, 2, 3, 7, 32, 64):
+    for rows in (0, 1, 2, 3, 7, 32, 64):
         announce(name, "rows", rows, prec)
         _, lat = make(name, nx, ny, prec=prec, rows=rows)
-        assert lat.launch_shape()[0] == min(rows, ny)
+        assert lat.launch_shape()[0] == (8 if rows == 0 else min(rows, ny))
         lat.set_populations(f0)
         lat.step(3)
         outs.append(lat.get_populations())
@@ -407,13 +408,13 @@ def test_full_size_tgv_1024x2048_sampled_and_shape_invariance():
                                       (L.LBM_FP32_DEV_F64, 1e-6)])
 def test_full_size_shear_layer_2048x8192_sampled(prec, tol):
     """The 2048 x 8192, r = 0.25 doubly periodic shear layer: buffers beyond
-    the Infinity Cache (non-temporal stores), 8 rows per wavefront."""
+    the Infinity Cache (non-temporal stores), tile kernel with 16-row tiles."""
     nx, ny, a, cs2 = 2048, 8192, 0.25, 0.04
     rates = O.paper_rates(1e-4 / cs2 + 0.5)
     p = O.make_params(nx, ny, a, cs2, rates)
     announce("full shear", prec)
     lat = L.Lattice(nx, ny, a, rates, cs2=cs2, precision=prec)
-    assert lat.launch_shape()[0] == 8
+    assert lat.launch_shape()[0] == 16
     lat.set_fields(*I.shear_layer(nx, ny, a))
     lat.step(5)
     f_before = lat.get_populations()
