@@ -195,6 +195,39 @@ __device__ __forceinline__ void load_interior(const S *__restrict__ src, const G
     }
 }
 
+// load_interior for a node whose row and the rows it pulls from are interior
+// but which may sit on the first or last column: a link from beyond an x
+// face wraps (periodic: a per-lane shift of the column by nx) or bounces back
+// half-way (wall: the node's own opposite population less the wall term of
+// Eq. 57-59, from an extra load of its own opposite plane).
+template <typename S, typename R, bool PULL>
+__device__ __forceinline__ void load_edge(const S *__restrict__ src, const Geometry &G,
+                                          const Consts<R> &K, int j, int x, R (&f)[9]) {
+    constexpr uint32_t B = sizeof(S);
+    const uint32_t pb = static_cast<uint32_t>(G.plane) * B;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, 9u * pb);
+    const uint32_t obm = static_cast<uint32_t>(j * G.pitch + x - 1) * B;
+    const bool left = x == 0, right = x == G.nx - 1;
+    const bool lwall = left && G.bc[kXmin] != kPeriodic, rwall = right && G.bc[kXmax] != kPeriodic;
+    const uint32_t wrap = static_cast<uint32_t>(G.nx) * B;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = PULL ? cx_of(k) : 0, cy = PULL ? cy_of(k) : 0;
+        const uint32_t soff = static_cast<uint32_t>(k) * pb -
+                              static_cast<uint32_t>(cy * G.pitch) * B;
+        uint32_t voff = obm + (1 - cx) * B;
+        if (cx == 1 && left && !lwall) voff += wrap;
+        if (cx == -1 && right && !rwall) voff -= wrap;
+        f[k] = static_cast<R>(buf_load(static_cast<S *>(nullptr), rs, voff, soff));
+        if (cx != 0) {
+            const bool w = cx == 1 ? lwall : rwall;
+            const R bb = static_cast<R>(buf_load(static_cast<S *>(nullptr), rs, obm + B,
+                                                 static_cast<uint32_t>(opp_of(k)) * pb));
+            f[k] = w ? bb - K.dwall[cx == 1 ? kXmin : kXmax][k] : f[k];
+        }
+    }
+}
+
 template <typename S, typename R>
 __device__ __forceinline__ void store_node(S *__restrict__ dst, const Geometry &G, int j, int x,
                                            const R (&o)[9]) {
@@ -773,13 +806,16 @@ tile_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry 
     const int tc = min(tx, nact - 1), tr = min(ty, nrow - 1);
     const int x = x0 + tc, j = j0 + tr;
     const bool active = tx < nact && ty < nrow;
-    // every node pulled by the tile or its density ring interior, no mask:
-    // buffer loads without boundary logic
-    const bool fast = G.buf_ok && !G.mask && x0 >= 2 && x0 + nact + 1 < G.nx && j0 >= 2 &&
-                      j0 + nrow + 1 < G.ny;
+    // every node pulled by the tile or its density ring in interior rows and
+    // no mask: buffer loads, with the x faces handled per lane on the first
+    // and last column tiles; anything else takes the generic loader
+    const bool rows_in = G.buf_ok && !G.mask && j0 >= 2 && j0 + nrow + 1 < G.ny;
+    const bool cols_in = x0 >= 2 && x0 + nact + 1 < G.nx;
     auto load = [&](int xx, int jj, R (&f)[9]) {
-        if (fast)
+        if (rows_in && cols_in)
             load_interior<S, R, PULL>(src, G, jj, xx, f);
+        else if (rows_in)
+            load_edge<S, R, PULL>(src, G, K, jj, xx, f);
         else
             load_node<S, R, PULL>(src, G, K, row_info(jj, G), col_info(xx, G), f);
     };
