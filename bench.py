@@ -205,6 +205,7 @@ def bench_sweep(args):
     stream = torch.cuda.Stream()
     b = L.Batch(cases, precision=prec, graph_steps=args.graph_steps, stream=stream.cuda_stream)
     rows, wgs = b.autotune(5)
+    tile = b.uses_tile_kernel()
     steps = (args.steps + args.graph_steps - 1) // args.graph_steps * args.graph_steps
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -242,7 +243,8 @@ def bench_sweep(args):
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "algorithmic_bytes_per_launch": bytes_per_lu * nodes,
-            "kernel": "lbm::batch_step_kernel", "bytes_per_lu": bytes_per_lu,
+            "kernel": "lbm::batch_tile_kernel" if tile else "lbm::batch_step_kernel",
+            "bytes_per_lu": bytes_per_lu,
             "kernel_us": round(1e3 * kern_ms, 3),
         },
         "unstable_cases": int(np.isnan(R).sum()),

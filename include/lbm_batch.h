@@ -48,6 +48,10 @@ typedef struct {
     int graph_steps;     /* steps per captured graph, even, >= 2; 0 => 64 */
     void *stream;        /* hipStream_t; NULL => the batch creates its own (graphs
                             cannot be captured on the null stream) */
+    int tile_kernel;     /* 1: step with the one-node-per-thread tile kernel from the
+                            start (the marching kernel while any case has a mask);
+                            0 (default): the marching kernel until lbm_batch_autotune
+                            chooses */
 } lbm_batch_opts;
 
 typedef struct lbm_batch lbm_batch;
@@ -122,12 +126,19 @@ int lbm_batch_set_populations(lbm_batch *b, int c, const double *f);
 long lbm_batch_steps_done(const lbm_batch *b, int c);
 
 /* Times the batched step over candidate launch shapes (rows per wavefront x
- * persistent grid size), trial_steps >= 1 launches each, and keeps the
- * fastest.  The trial launches recompute one step from the current state
+ * persistent grid size of the marching kernel, and, when no case has a mask,
+ * the one-node-per-thread tile kernel on 64 x 8 block tiles with three grid
+ * sizes; it then reports 8 rows), trial_steps >= 1 launches each, and keeps
+ * the fastest.  Setting a mask later returns the batch to the marching
+ * kernel.  The trial launches recompute one step from the current state
  * without committing it, so no case advances; the residual of every case
  * needs a step afterwards.  rows_out / workgroups_out (may be NULL) receive
  * the choice.  Synchronizes.  Errors: LBM_E_INVAL, LBM_E_DEVICE. */
 int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out, int *workgroups_out);
+
+/* 1 if the batch steps with the tile kernel (chosen by lbm_batch_autotune
+ * when no case has a mask), 0 for the marching kernel; -1 for a NULL batch. */
+int lbm_batch_uses_tile_kernel(const lbm_batch *b);
 
 /* Current launch shape: rows per wavefront, persistent workgroups and the
  * number of tiles of the active cases.  Errors: LBM_E_INVAL. */

@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -65,6 +66,7 @@ struct lbm_batch {
     double *d_stage;
     size_t stage_bytes;
     // launch shape
+    bool tile_mode;             // the batched tile kernel (64 x kBatchTileRows block tiles)
     int rows;
     int workgroups;
     int graph_steps;
@@ -107,13 +109,36 @@ static int auto_workgroups(int ntiles) {
     return wgs < 1 ? 1 : wgs;
 }
 
-// Tile list of the active cases, uploaded with its count.
+static bool any_mask(const lbm_batch *b) {
+    for (int c = 0; c < b->n; ++c)
+        if (!b->hmask[c].empty()) return true;
+    return false;
+}
+
+// block tiles of the batched tile kernel for one case
+static int block_tiles(const Geometry &G) {
+    return G.nseg * ((G.ny + kBatchTileRows - 1) / kBatchTileRows);
+}
+
+// Tile list of the active cases, uploaded with its count: block tiles in tile
+// mode, wavefront tiles of the march otherwise.  A mask on any case ends tile
+// mode (its generic loads would be slower than the march's near-solid tiles).
 static int upload_tiles(lbm_batch *b) {
+    if (b->tile_mode && any_mask(b)) {
+        b->tile_mode = false;
+        b->graph_ok = false;
+    }
     std::vector<BatchTile> t;
     t.reserve(b->tile_cap);
     for (int c = 0; c < b->n; ++c) {
         if (!b->active[c]) continue;
         const Geometry &G = b->G[c];
+        if (b->tile_mode) {
+            const int nty = (G.ny + kBatchTileRows - 1) / kBatchTileRows;
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < G.nseg; ++tx) t.push_back(BatchTile{c, tx, ty, 0});
+            continue;
+        }
         const unsigned char *m = b->hmask[c].empty() ? nullptr : b->hmask[c].data();
         for (int ch = 0; ch < G.nchunk; ++ch)
             for (int s = 0; s < G.nseg; ++s)
@@ -151,7 +176,7 @@ static int apply_rows(lbm_batch *b, int rows) {
     int cap = 0;
     for (int c = 0; c < b->n; ++c) {
         set_rows(b->G[c], rows);
-        cap += b->G[c].ntile;
+        cap += std::max(b->G[c].ntile, block_tiles(b->G[c]));
     }
     if (cap > b->tile_cap) {
         if (b->d_tiles) HIP_OK(b, hipFree(b->d_tiles));
@@ -168,6 +193,10 @@ static int apply_rows(lbm_batch *b, int rows) {
 }
 
 static hipError_t launch(lbm_batch *b, int flip, int force_pull, int wgs) {
+    if (b->tile_mode)
+        return launch_batch_tile(b->prec, b->coll, b->higher_unit, b->buf[0], b->buf[1],
+                                 b->d_tiles, b->d_ntiles, b->d_cases, b->d_geoms, b->d_Kd,
+                                 b->d_Kf, flip, force_pull, wgs, b->stream);
     return launch_batch_step(b->prec, b->coll, b->higher_unit, b->buf[0], b->buf[1], b->d_tiles,
                              b->d_ntiles, b->d_cases, b->d_geoms, b->d_Kd, b->d_Kf, flip,
                              force_pull, wgs, b->stream);
@@ -375,6 +404,7 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
         int r = upload_cases(b);
         if (r != LBM_OK) return r;
         const int rows = o.rows_per_wave > 0 ? o.rows_per_wave : auto_rows(nodes, o.precision);
+        b->tile_mode = o.tile_kernel == 1;
         r = apply_rows(b, rows);
         if (r != LBM_OK) return r;
         b->workgroups = o.workgroups > 0 ? o.workgroups : auto_workgroups(b->ntiles);
@@ -738,11 +768,12 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
             int wgs = m ? 256 * m : (b->ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
             const int need = (b->ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
             if (wgs > need) wgs = need;
-            // one untimed launch, then trial_steps timed ones; flip 0 and the
-            // per-case forms: every trial recomputes the same step
-            hipError_t e = launch(b, 0, 0, wgs);
+            // one untimed launch, then trial_steps timed ones; flip 0: every
+            // trial recomputes the same step into the other buffer.  Timed in
+            // the pull form that the captured steps run (values are not kept)
+            hipError_t e = launch(b, 0, 1, wgs);
             if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            for (int i = 0; i < trial_steps && e == hipSuccess; ++i) e = launch(b, 0, 0, wgs);
+            for (int i = 0; i < trial_steps && e == hipSuccess; ++i) e = launch(b, 0, 1, wgs);
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
@@ -759,11 +790,46 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
         }
         if (rc != LBM_OK) break;
     }
+    // the batched tile kernel (no masks): one block tile per workgroup, or a
+    // persistent grid of 4 or 8 workgroups per CU
+    bool best_tile = false;
+    if (rc == LBM_OK && !any_mask(b)) {
+        b->tile_mode = true;
+        rc = upload_tiles(b);
+        const int nbt = b->ntiles;
+        for (int wgs : {nbt, 256 * 8, 256 * 4}) {
+            if (rc != LBM_OK || nbt == 0) break;
+            if (wgs > nbt) wgs = nbt;
+            hipError_t e = launch(b, 0, 1, wgs);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int i = 0; i < trial_steps && e == hipSuccess; ++i) e = launch(b, 0, 1, wgs);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(b, LBM_E_DEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_tile = true;
+                best_rows = kBatchTileRows;
+                best_wgs = wgs;
+            }
+        }
+        b->tile_mode = false;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LBM_OK) return rc;
-    rc = apply_rows(b, best_rows);
+    rc = apply_rows(b, best_tile ? 4 : best_rows);  // (tile mode keeps 4-row march tiles as fallback)
     if (rc != LBM_OK) return rc;
+    if (best_tile) {
+        b->tile_mode = true;
+        rc = upload_tiles(b);
+        if (rc != LBM_OK) return rc;
+    }
     b->workgroups = best_wgs;
     b->graph_ok = false;
     // the other buffer of every case was overwritten by the trials
@@ -776,16 +842,23 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
 extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, int *workgroups,
                                       int *tiles) {
     if (!b) return LBM_E_INVAL;
-    if (rows_per_wave) *rows_per_wave = b->rows;
+    // (tile mode reports its block-tile rows and block tiles)
+    const bool tile = b->tile_mode && !any_mask(b);
+    if (rows_per_wave) *rows_per_wave = tile ? kBatchTileRows : b->rows;
     if (workgroups) *workgroups = b->workgroups;
     if (tiles) {
         // count without touching the device when the list is stale
         int t = 0;
         for (int c = 0; c < b->n; ++c)
-            if (b->active[c]) t += b->G[c].ntile;
+            if (b->active[c]) t += tile ? block_tiles(b->G[c]) : b->G[c].ntile;
         *tiles = t;
     }
     return LBM_OK;
+}
+
+extern "C" int lbm_batch_uses_tile_kernel(const lbm_batch *b) {
+    if (!b) return -1;
+    return b->tile_mode && !any_mask(b) ? 1 : 0;
 }
 
 extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {

@@ -99,6 +99,7 @@ struct BatchRed {
     int c, start, count, flags;  // flags: bit 0 pc, bit 1 pp
 };
 constexpr int kBatchRedNodes = 4096;  // nodes per reduction work item
+constexpr int kBatchTileRows = 8;     // rows of a block tile of the batched tile kernel
 
 // ---- host helpers shared by the single-lattice and batch front ends ----
 // (implemented in lbm_api.hip; the lbm.h types are opaque here)
@@ -169,6 +170,13 @@ hipError_t launch_batch_step(int prec, int coll, bool higher_unit, void *buf0, v
                              const Geometry *geoms,
                              const Consts<double> *Kd, const Consts<float> *Kf, int flip,
                              int force_pull, int workgroups, hipStream_t st);
+// batched tile kernel over a list of 64 x kBatchTileRows block tiles
+// (BatchTile {case, tile column, tile row}) on a persistent grid of `workgroups`
+hipError_t launch_batch_tile(int prec, int coll, bool higher_unit, void *buf0, void *buf1,
+                             const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                             const Geometry *geoms, const Consts<double> *Kd,
+                             const Consts<float> *Kf, int flip, int force_pull, int workgroups,
+                             hipStream_t st);
 // per-case residual sums of the batch: out[4 c + 0..3] as for launch_residual,
 // over the cases named by the reduction items (items of a case are contiguous)
 hipError_t launch_batch_residual(int prec, const void *buf0, const void *buf1,

@@ -791,17 +791,11 @@ __device__ __forceinline__ int nb_row(int j, int d, const Geometry &G) {
 // serial dependence between rows, so every load of the tile is in flight at
 // once: the shape for lattices that fit the Infinity Cache.
 template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU, int TY>
-__global__ void __launch_bounds__(kWave * TY)
-tile_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
-                 const Consts<R> K, int ntx, int nty) {
-    __shared__ R srho[TY + 2][kWave + 2];
+__device__ __forceinline__ void tile_body(const S *__restrict__ src, S *__restrict__ dst,
+                                          const Geometry &G, const Consts<R> &K, int x0, int j0,
+                                          R (&srho)[TY + 2][kWave + 2]) {
     const int tx = threadIdx.x & (kWave - 1);
     const int ty = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    int b = blockIdx.x;
-    const int nb = static_cast<int>(gridDim.x);
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
-    if (b >= ntx * nty) return;                             // padding workgroup (whole block)
-    const int x0 = (b % ntx) * kWave, j0 = (b / ntx) * TY;
     const int nact = min(kWave, G.nx - x0), nrow = min(TY, G.ny - j0);
     const int tc = min(tx, nact - 1), tr = min(ty, nrow - 1);
     const int x = x0 + tc, j = j0 + tr;
@@ -879,10 +873,86 @@ tile_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry 
     if (active) store_node(dst, G, j, x, out);
 }
 
+template <typename S, typename R, bool DEV, int COLL, bool PULL, bool HU, int TY>
+__global__ void __launch_bounds__(kWave * TY)
+tile_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
+                 const Consts<R> K, int ntx, int nty) {
+    __shared__ R srho[TY + 2][kWave + 2];
+    int b = blockIdx.x;
+    const int nb = static_cast<int>(gridDim.x);
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
+    if (b >= ntx * nty) return;                             // padding workgroup (whole block)
+    tile_body<S, R, DEV, COLL, PULL, HU, TY>(src, dst, G, K, (b % ntx) * kWave, (b / ntx) * TY,
+                                             srho);
+}
+
+// Batched form: a persistent grid walks a list of 64 x TY block tiles of all
+// active cases (BatchTile {case, tile column, tile row}); the LDS tile is
+// reused, with a barrier between tiles.
+template <typename S, typename R, bool DEV, int COLL, bool HU, int TY>
+__global__ void __launch_bounds__(kWave * TY)
+batch_tile_kernel(S *__restrict__ buf0, S *__restrict__ buf1, const BatchTile *__restrict__ tiles,
+                  const int *__restrict__ ntiles, const BatchCase *__restrict__ cases,
+                  const Geometry *__restrict__ geoms, const Consts<R> *__restrict__ Ks, int flip,
+                  int force_pull) {
+    __shared__ R srho[TY + 2][kWave + 2];
+    const int n = *ntiles;
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const BatchTile td = tiles[t];
+        const int c = __builtin_amdgcn_readfirstlane(td.c);
+        const int tcol = __builtin_amdgcn_readfirstlane(td.seg);
+        const int trow = __builtin_amdgcn_readfirstlane(td.chunk);
+        const Geometry &G = geoms[c];
+        const Consts<R> &K = Ks[c];
+        const int cur = __builtin_amdgcn_readfirstlane(cases[c].cur) ^ flip;
+        const long long off = cases[c].off;
+        const S *src = (cur ? buf1 : buf0) + off;
+        S *dst = (cur ? buf0 : buf1) + off;
+        if (force_pull || cases[c].pull)
+            tile_body<S, R, DEV, COLL, true, HU, TY>(src, dst, G, K, tcol * kWave, trow * TY, srho);
+        else
+            tile_body<S, R, DEV, COLL, false, HU, TY>(src, dst, G, K, tcol * kWave, trow * TY, srho);
+        __syncthreads();  // the next tile reuses the LDS tile
+    }
+}
+
 int tile_workgroups(const Geometry &G) {
     const int ty = G.tile_rows == 16 ? 16 : 8;
     const int n = ((G.nx + kWave - 1) / kWave) * ((G.ny + ty - 1) / ty);
     return (n + 7) / 8 * 8;
+}
+
+template <typename S, typename R, bool DEV>
+static hipError_t batch_tile_dispatch(int coll, bool hu, void *b0, void *b1, const BatchTile *tiles,
+                                      const int *ntiles, const BatchCase *cases,
+                                      const Geometry *geoms, const Consts<R> *K, int flip,
+                                      int force_pull, int wgs, hipStream_t st) {
+    const dim3 grid(wgs), block(kWave * kBatchTileRows);
+#define LBM_BTILE(C, H)                                                                          \
+    hipLaunchKernelGGL((batch_tile_kernel<S, R, DEV, C, H, kBatchTileRows>), grid, block, 0, st,  \
+                       static_cast<S *>(b0), static_cast<S *>(b1), tiles, ntiles, cases, geoms,   \
+                       K, flip, force_pull)
+    if (coll == kRC) {
+        if (hu) LBM_BTILE(kRC, true); else LBM_BTILE(kRC, false);
+    } else {
+        if (hu) LBM_BTILE(kRNR, true); else LBM_BTILE(kRNR, false);
+    }
+#undef LBM_BTILE
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile(int prec, int coll, bool hu, void *b0, void *b1,
+                             const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                             const Geometry *geoms, const Consts<double> *Kd,
+                             const Consts<float> *Kf, int flip, int force_pull, int wgs,
+                             hipStream_t st) {
+    switch (prec) {
+    case kFP64: return batch_tile_dispatch<double, double, false>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, force_pull, wgs, st);
+    case kFP32Dev: return batch_tile_dispatch<float, float, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kf, flip, force_pull, wgs, st);
+    case kFP64Dev: return batch_tile_dispatch<double, double, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, force_pull, wgs, st);
+    case kFP32DevF64: return batch_tile_dispatch<float, double, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, force_pull, wgs, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename S, typename R, bool DEV>
