@@ -66,7 +66,9 @@ struct lbm_batch {
     double *d_stage;
     size_t stage_bytes;
     // launch shape
-    bool tile_mode;             // the batched tile kernel (64 x kBatchTileRows block tiles)
+    bool tile_pref;             // the tile kernel is wanted (option or autotuner)
+    bool tile_mode;             // the batched tile kernel runs (64 x kBatchTileRows block
+                                // tiles): tile_pref and no case has a mask
     int rows;
     int workgroups;
     int graph_steps;
@@ -124,9 +126,10 @@ static int block_tiles(const Geometry &G) {
 // mode, wavefront tiles of the march otherwise.  A mask on any case ends tile
 // mode (its generic loads would be slower than the march's near-solid tiles).
 static int upload_tiles(lbm_batch *b) {
-    if (b->tile_mode && any_mask(b)) {
-        b->tile_mode = false;
-        b->graph_ok = false;
+    const bool mode = b->tile_pref && !any_mask(b);
+    if (mode != b->tile_mode) {
+        b->tile_mode = mode;
+        b->graph_ok = false;  // the captured steps launch the other kernel
     }
     std::vector<BatchTile> t;
     t.reserve(b->tile_cap);
@@ -404,7 +407,7 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
         int r = upload_cases(b);
         if (r != LBM_OK) return r;
         const int rows = o.rows_per_wave > 0 ? o.rows_per_wave : auto_rows(nodes, o.precision);
-        b->tile_mode = o.tile_kernel == 1;
+        b->tile_pref = o.tile_kernel == 1;
         r = apply_rows(b, rows);
         if (r != LBM_OK) return r;
         b->workgroups = o.workgroups > 0 ? o.workgroups : auto_workgroups(b->ntiles);
@@ -752,6 +755,7 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
                                   int *workgroups_out) {
     if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
     if (trial_steps < 1) return fail(b, LBM_E_INVAL, "trial_steps must be >= 1");
+    b->tile_pref = false;  // the march candidates first
     const int rows_c[] = {2, 4, 8, 16};
     const int wg_mult[] = {2, 4, 8, 0};  // x 256 CUs; 0: one tile per wavefront
     hipEvent_t e0, e1;
@@ -794,7 +798,7 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
     // persistent grid of 4 or 8 workgroups per CU
     bool best_tile = false;
     if (rc == LBM_OK && !any_mask(b)) {
-        b->tile_mode = true;
+        b->tile_pref = true;
         rc = upload_tiles(b);
         const int nbt = b->ntiles;
         for (int wgs : {nbt, 256 * 8, 256 * 4}) {
@@ -818,18 +822,14 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
                 best_wgs = wgs;
             }
         }
-        b->tile_mode = false;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LBM_OK) return rc;
-    rc = apply_rows(b, best_tile ? 4 : best_rows);  // (tile mode keeps 4-row march tiles as fallback)
+    b->tile_pref = best_tile;
+    // (tile mode keeps 4-row march tiles for when a mask appears)
+    rc = apply_rows(b, best_tile ? 4 : best_rows);
     if (rc != LBM_OK) return rc;
-    if (best_tile) {
-        b->tile_mode = true;
-        rc = upload_tiles(b);
-        if (rc != LBM_OK) return rc;
-    }
     b->workgroups = best_wgs;
     b->graph_ok = false;
     // the other buffer of every case was overwritten by the trials
@@ -843,7 +843,7 @@ extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, in
                                       int *tiles) {
     if (!b) return LBM_E_INVAL;
     // (tile mode reports its block-tile rows and block tiles)
-    const bool tile = b->tile_mode && !any_mask(b);
+    const bool tile = b->tile_pref && !any_mask(b);
     if (rows_per_wave) *rows_per_wave = tile ? kBatchTileRows : b->rows;
     if (workgroups) *workgroups = b->workgroups;
     if (tiles) {
@@ -858,7 +858,7 @@ extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, in
 
 extern "C" int lbm_batch_uses_tile_kernel(const lbm_batch *b) {
     if (!b) return -1;
-    return b->tile_mode && !any_mask(b) ? 1 : 0;
+    return b->tile_pref && !any_mask(b) ? 1 : 0;
 }
 
 extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {

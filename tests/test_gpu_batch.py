@@ -292,3 +292,25 @@ def test_tile_kernel_batch_matches_single_lattices_and_falls_back_under_a_mask(p
     assert np.array_equal(b.get_populations(0), lat.get_populations())
     lat.close()
     b.close()
+
+
+def test_tile_kernel_returns_when_the_masks_are_removed():
+    announce("batch tile kernel after masks")
+    b = L.Batch(cases_of(SPECS[:2]), graph_steps=4, tile_kernel=True)
+    nx, ny = b.shapes[1]
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[5:8, 10:14] = 1
+    b.set_mask(1, mask)
+    assert not b.uses_tile_kernel()
+    b.step(6)
+    b.set_mask(1, None)
+    assert b.uses_tile_kernel()
+    b.step(6)
+    lat = single(SPECS[1], L.LBM_RC, L.LBM_FP64)
+    lat.set_mask(mask)
+    lat.step(6)
+    lat.set_mask(None)
+    lat.step(6)
+    assert np.array_equal(b.get_populations(1), lat.get_populations())
+    lat.close()
+    b.close()
