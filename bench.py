@@ -307,8 +307,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the lattice step shards by slabs "
-              "with halo exchange (see the design notes), which is not built here.",
+        print("bench.py: the library runs on one GPU only; a multi-GPU lattice step would "
+              "shard by slabs with a halo exchange, which is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
