@@ -6,7 +6,8 @@ ny 1024 nodes at aspect ratio r = dy/dx = 0.5, Re 1000, lid speed 0.05,
 FP32-deviation storage, RC collision (the raw-moment RNR variant is timed
 beside it).  A step is one collide-and-stream pass over the whole lattice;
 every `--check-every` steps the FP64 residual and conservation reductions run
-inside the timed region, as in a run to steady state.  Inputs (the cavity at
+inside the timed region, as in a run to steady state (enqueued without a host
+wait and read one interval later, as a monitored production run would).  Inputs (the cavity at
 rest, after the warm-up steps) are resident in HBM when timing starts.
 
 Prints ONE JSON line: MLUPS of the whole job, the roofline of the step kernel
@@ -73,9 +74,12 @@ def setup(name, precision, collision, rows=0):
 def time_steps(lat, steps, check_every, chunk):
     """Times `steps` steps issued `chunk` launches at a time (one C-level
     loop per chunk), each chunk bracketed by HIP events on torch's current
-    stream (the stream the library enqueues on); the FP64 residual and sums
-    run every `check_every` steps.  Returns the wall time, the per-launch
-    kernel times from the events and the first step at which a reduction
+    stream (the stream the library enqueues on).  Every `check_every` steps
+    the FP64 residual and conservation reductions are enqueued without a
+    host wait (lbm_check_async), and the previous check's results are read
+    then, one interval later, so the queue never drains; the last one is
+    read before the clock stops.  Returns the wall time, the per-launch
+    kernel times from the events and the step of the first check that
     reported a non-finite field (None if none did)."""
     import torch
 
@@ -87,6 +91,17 @@ def time_steps(lat, steps, check_every, chunk):
           for _ in range(nchunks)]
     sizes = []
     blew_up = None
+    pending = None  # steps done at the enqueued, unread check
+
+    def read():
+        nonlocal blew_up
+        try:
+            lat.check_result()
+        except L.LbmError as e:
+            if e.code != L.LBM_E_UNSTABLE:
+                raise
+            blew_up = pending
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
@@ -98,13 +113,12 @@ def time_steps(lat, steps, check_every, chunk):
         sizes.append(n)
         done += n
         if check_every and done % check_every == 0 and blew_up is None:
-            try:
-                lat.residual()
-                lat.sums()
-            except L.LbmError as e:
-                if e.code != L.LBM_E_UNSTABLE:
-                    raise
-                blew_up = done
+            if pending is not None:
+                read()
+            lat.check_async()
+            pending = done
+    if pending is not None and blew_up is None:
+        read()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_launch = [a.elapsed_time(b) / n for (a, b), n in zip(ev, sizes)]

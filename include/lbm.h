@@ -161,6 +161,20 @@ int lbm_stress(lbm_ctx *ctx, double *sxx, double *syy, double *sxy);
  * LBM_E_DEVICE. */
 int lbm_sums(lbm_ctx *ctx, double out[3]);
 
+/* lbm_residual and lbm_sums of the current time level without a host wait,
+ * for monitoring a run while it runs: check_async enqueues both reductions
+ * and a copy of their results to pinned host memory the context owns, and
+ * returns; check_result waits only for the latest enqueued check (the steps
+ * enqueued after it keep the GPU busy) and returns R, sums[0..2] and the step
+ * count at which it was taken.  A later check_async replaces the pending one.
+ * R, sums and step may be NULL.
+ * Errors: check_async: LBM_E_STATE before the first step (as lbm_residual),
+ * LBM_E_NOMEM (pinned buffer), LBM_E_DEVICE.  check_result: LBM_E_STATE if no
+ * check was enqueued; LBM_E_UNSTABLE if a density or velocity was NaN or Inf
+ * (*R is then NaN; *step names the check); LBM_E_DEVICE. */
+int lbm_check_async(lbm_ctx *ctx);
+int lbm_check_result(lbm_ctx *ctx, double *R, double sums[3], long *step);
+
 /* Copies the populations f_i(x, t) of the current time level (after
  * streaming, before collision) to / from host double[9][ny][nx].
  * set_populations replaces the state and synchronizes; get synchronizes.

@@ -44,6 +44,9 @@ struct lbm_ctx {
     int form[2];      // Form of each buffer's contents
     int prev_valid;   // the other buffer holds the state one step earlier
     double *d_partials;  // reduction partials + results
+    double *h_check;     // pinned host copy of the last lbm_check_async (lazy)
+    hipEvent_t check_ev; // recorded after that copy
+    long check_step;     // steps done when it was enqueued; -1 = none
     double *d_stage;     // FP64 staging for host transfers (lazy)
     size_t stage_bytes;
     unsigned char *d_mask;        // obstacle mask [ny][pitch] (or null)
@@ -340,6 +343,7 @@ extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail_ctx(nullptr, LBM_E_NOMEM, "out of host memory");
+    c->check_step = -1;
     c->nx = nx;
     c->ny = ny;
     c->a = r;
@@ -515,6 +519,58 @@ extern "C" int lbm_residual(lbm_ctx *c, double *R) {
     return LBM_OK;
 }
 
+// Residual and sums of one time level without a host wait: both reductions
+// write their four results to their own slots behind the partials, and one
+// copy takes the eight values to pinned host memory.  The reductions run in
+// stream order, so a later check or a synchronous lbm_residual / lbm_sums
+// reusing the partials cannot overtake them.
+extern "C" int lbm_check_async(lbm_ctx *c) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!c->prev_valid || c->form[1 - c->cur] == kEmpty)
+        return fail_ctx(c, LBM_E_STATE, "no step taken since the state was set");
+    if (!c->h_check) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, 8 * sizeof(double)) != hipSuccess || !h)
+            return fail_ctx(c, LBM_E_NOMEM, "pinned host buffer for the check");
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(h);
+            return fail_ctx(c, LBM_E_DEVICE, "hipEventCreateWithFlags failed");
+        }
+        c->h_check = static_cast<double *>(h);
+        c->check_ev = ev;
+    }
+    const int p = 1 - c->cur;
+    const bool pull = c->form[c->cur] == kPost;
+    double *res = c->d_partials + 4 * kMaxPartials;
+    HIP_OR_FAIL(c, launch_residual(c->prec, pull, c->f[c->cur], c->form[p] == kPost, c->f[p],
+                                   c->d_partials, res, c->G, c->Kd, c->Kf, c->H, c->stream));
+    HIP_OR_FAIL(c, launch_sums(c->prec, pull, c->f[c->cur], c->d_partials, res + 4, c->G, c->Kd,
+                               c->Kf, c->H, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->h_check, res, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipEventRecord(c->check_ev, c->stream));
+    c->check_step = c->steps;
+    return LBM_OK;
+}
+
+extern "C" int lbm_check_result(lbm_ctx *c, double *R, double sums[3], long *step) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (c->check_step < 0) return fail_ctx(c, LBM_E_STATE, "no check enqueued");
+    HIP_OR_FAIL(c, hipEventSynchronize(c->check_ev));
+    const double *r = c->h_check;
+    if (step) *step = c->check_step;
+    if (sums)
+        for (int i = 0; i < 3; ++i) sums[i] = r[4 + i];
+    const bool bad = r[3] != 0.0 || r[7] != 0.0 || !isfinite(r[0]) || !isfinite(r[1]) ||
+                     !isfinite(r[4]) || !isfinite(r[5]) || !isfinite(r[6]);
+    if (R) *R = bad ? NAN : (r[1] > 0.0 ? sqrt(r[0]) / sqrt(r[1]) : (r[0] > 0.0 ? INFINITY : 0.0));
+    if (bad)
+        return fail_ctx(c, LBM_E_UNSTABLE, "non-finite density or velocity at step %ld",
+                        c->check_step);
+    return LBM_OK;
+}
+
 extern "C" int lbm_get_populations(lbm_ctx *c, double *f) {
     if (!c || !f) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
     const size_t n9 = static_cast<size_t>(9) * c->nx * c->ny;
@@ -673,6 +729,8 @@ extern "C" int lbm_destroy(lbm_ctx *c) {
     for (int i = 0; i < 2; ++i)
         if (c->owns[i] && c->f[i]) (void)hipFree(c->f[i]);
     if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->h_check) (void)hipHostFree(c->h_check);
+    if (c->check_ev) (void)hipEventDestroy(c->check_ev);
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_mask) (void)hipFree(c->d_mask);
     if (c->d_tile_solid) (void)hipFree(c->d_tile_solid);

@@ -26,12 +26,10 @@ LBM_RC, LBM_RNR = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
-           "lbm_moments", "lbm_stress", "lbm_residual", "lbm_sums", "lbm_get_populations",
-           "lbm_set_populations", "lbm_set_mask", "lbm_set_rates", "lbm_set_force",
-           "lbm_step_forced", "lbm_smooth_step",
-           "lbm_steps_done",
-           "lbm_launch_shape",
-           "lbm_last_error", "lbm_destroy")
+           "lbm_moments", "lbm_stress", "lbm_residual", "lbm_sums", "lbm_check_async",
+           "lbm_check_result", "lbm_get_populations", "lbm_set_populations", "lbm_set_mask",
+           "lbm_set_rates", "lbm_set_force", "lbm_step_forced", "lbm_smooth_step",
+           "lbm_steps_done", "lbm_launch_shape", "lbm_last_error", "lbm_destroy")
 BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fields",
                  "lbm_batch_set_mask", "lbm_batch_set_rates", "lbm_batch_smooth_step",
                  "lbm_batch_set_active", "lbm_batch_step", "lbm_batch_residuals",
@@ -127,6 +125,11 @@ def load():
     L.lbm_stress.argtypes = [_CTX, _D, _D, _D]
     L.lbm_residual.argtypes = [_CTX, _D]
     L.lbm_sums.argtypes = [_CTX, _D]
+    L.lbm_check_async.argtypes = [_CTX]
+    L.lbm_check_async.restype = ctypes.c_int
+    L.lbm_check_result.argtypes = [_CTX, ctypes.POINTER(ctypes.c_double), _D,
+                                   ctypes.POINTER(ctypes.c_long)]
+    L.lbm_check_result.restype = ctypes.c_int
     L.lbm_get_populations.argtypes = [_CTX, _D]
     L.lbm_set_populations.argtypes = [_CTX, _D]
     _U8 = ctypes.POINTER(ctypes.c_ubyte)
@@ -272,6 +275,18 @@ def lbm_sums(ctx):
     return out
 
 
+def lbm_check_async(ctx):
+    _check(load().lbm_check_async(ctx), ctx)
+
+
+def lbm_check_result(ctx):
+    """(R, sums, step) of the latest lbm_check_async."""
+    R, step, out = ctypes.c_double(), ctypes.c_long(), np.zeros(3)
+    _check(load().lbm_check_result(ctx, ctypes.byref(R), out.ctypes.data_as(_D),
+                                   ctypes.byref(step)), ctx)
+    return R.value, out, step.value
+
+
 def lbm_get_populations(ctx, nx, ny):
     f = np.empty((9, ny, nx))
     _check(load().lbm_get_populations(ctx, f.ctypes.data_as(_D)), ctx)
@@ -387,6 +402,12 @@ class Lattice:
 
     def sums(self):
         return lbm_sums(self.ctx)
+
+    def check_async(self):
+        lbm_check_async(self.ctx)
+
+    def check_result(self):
+        return lbm_check_result(self.ctx)
 
     def get_populations(self):
         return lbm_get_populations(self.ctx, self.nx, self.ny)

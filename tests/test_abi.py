@@ -202,6 +202,8 @@ def test_null_handles_are_rejected_before_touching_the_device():
         "lbm_stress": (None, None, None, None),
         "lbm_sums": (None, pd),
         "lbm_residual": (None, pd),
+        "lbm_check_async": (None,),
+        "lbm_check_result": (None, pd, pd, None),
         "lbm_get_populations": (None, pd),
         "lbm_set_populations": (None, pd),
         "lbm_set_mask": (None, None),

@@ -218,6 +218,41 @@ def test_first_step_residual_and_unstable_flag():
     lat.close()
 
 
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+def test_async_check_matches_the_synchronous_reductions(prec):
+    """check_async / check_result give the residual and sums that residual()
+    and sums() give for the same time level (the same deterministic
+    reductions, so bit for bit), read while later steps are enqueued; the
+    step count names the level; a NaN is reported as unstable."""
+    p, lat = make("cavity", 150, 70, prec=prec)
+    lat.set_populations(random_state(p, seed=23))
+    for call in (lat.check_async, lat.check_result):
+        with pytest.raises(L.LbmError) as e:
+            call()
+        assert e.value.code == L.LBM_E_STATE
+    lat.step(7)
+    at = lat.steps_done
+    R7, S7 = lat.residual(), lat.sums()
+    lat.check_async()
+    lat.step(50)
+    R, S, step = lat.check_result()
+    assert step == at and R == R7 and np.array_equal(S, S7)
+    R57, S57 = lat.residual(), lat.sums()
+    lat.check_async()
+    lat.check_async()
+    R, S, step = lat.check_result()
+    assert step == at + 50 and R == R57 and np.array_equal(S, S57)
+    f = lat.get_populations()
+    f[3, 5, 7] = np.nan
+    lat.set_populations(f)
+    lat.step(1)
+    lat.check_async()
+    with pytest.raises(L.LbmError) as e:
+        lat.check_result()
+    assert e.value.code == L.LBM_E_UNSTABLE
+    lat.close()
+
+
 # ---------------------------------------------------------------- FP32
 
 @pytest.mark.parametrize("prec", [L.LBM_FP32_DEV, L.LBM_FP32_DEV_F64])
