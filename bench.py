@@ -310,7 +310,7 @@ def main():
     ap.add_argument("--steady-every", type=int, default=1000)
     ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
     ap.add_argument("--check-every", type=int, default=100)
-    ap.add_argument("--chunk", type=int, default=10, help="launches per host call")
+    ap.add_argument("--chunk", type=int, default=100, help="launches per host call")
     ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0 = automatic)")
     ap.add_argument("--no-rnr", action="store_true", help="skip the RNR side-by-side timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -24,6 +24,9 @@ enum Form { kEmpty = 0, kPre = 1, kPost = 2 };
 
 }  // namespace
 
+// reduction partials (up to 8 values per block), then the results
+static constexpr size_t kResults = 8 * static_cast<size_t>(kMaxPartials);
+
 struct lbm_ctx {
     int nx, ny;
     double a;
@@ -382,7 +385,7 @@ extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const
         }
     }
     if (status == LBM_OK) {
-        hipError_t e = hipMalloc(&c->d_partials, (4 * kMaxPartials + 8) * sizeof(double));
+        hipError_t e = hipMalloc(&c->d_partials, (kResults + 8) * sizeof(double));
         if (e != hipSuccess) {
             c->d_partials = nullptr;
             status = fail_ctx(nullptr, LBM_E_DEVICE, "hipMalloc of partials failed: %s",
@@ -477,7 +480,7 @@ extern "C" int lbm_stress(lbm_ctx *c, double *sxx, double *syy, double *sxy) {
 }
 
 static int fetch_result(lbm_ctx *c, double out[4]) {
-    HIP_OR_FAIL(c, hipMemcpyAsync(out, c->d_partials + 4 * kMaxPartials, 4 * sizeof(double),
+    HIP_OR_FAIL(c, hipMemcpyAsync(out, c->d_partials + kResults, 4 * sizeof(double),
                                   hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
@@ -486,7 +489,7 @@ static int fetch_result(lbm_ctx *c, double out[4]) {
 extern "C" int lbm_sums(lbm_ctx *c, double out[3]) {
     if (!c || !out) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
     HIP_OR_FAIL(c, launch_sums(c->prec, c->form[c->cur] == kPost, c->f[c->cur], c->d_partials,
-                               c->d_partials + 4 * kMaxPartials, c->G, c->Kd, c->Kf, c->H,
+                               c->d_partials + kResults, c->G, c->Kd, c->Kf, c->H,
                                c->stream));
     double r[4];
     int rc = fetch_result(c, r);
@@ -506,7 +509,7 @@ extern "C" int lbm_residual(lbm_ctx *c, double *R) {
     const int p = 1 - c->cur;
     HIP_OR_FAIL(c, launch_residual(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
                                    c->form[p] == kPost, c->f[p], c->d_partials,
-                                   c->d_partials + 4 * kMaxPartials, c->G, c->Kd, c->Kf, c->H,
+                                   c->d_partials + kResults, c->G, c->Kd, c->Kf, c->H,
                                    c->stream));
     double r[4];
     int rc = fetch_result(c, r);
@@ -519,11 +522,11 @@ extern "C" int lbm_residual(lbm_ctx *c, double *R) {
     return LBM_OK;
 }
 
-// Residual and sums of one time level without a host wait: both reductions
-// write their four results to their own slots behind the partials, and one
-// copy takes the eight values to pinned host memory.  The reductions run in
-// stream order, so a later check or a synchronous lbm_residual / lbm_sums
-// reusing the partials cannot overtake them.
+// Residual and sums of one time level without a host wait: one pass over the
+// two buffers writes both results (eight values) behind the partials, and
+// one copy takes them to pinned host memory.  Everything runs in stream
+// order, so a later check or a synchronous lbm_residual / lbm_sums reusing
+// the partials cannot overtake it.
 extern "C" int lbm_check_async(lbm_ctx *c) {
     if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
     if (!c->prev_valid || c->form[1 - c->cur] == kEmpty)
@@ -541,12 +544,10 @@ extern "C" int lbm_check_async(lbm_ctx *c) {
         c->check_ev = ev;
     }
     const int p = 1 - c->cur;
-    const bool pull = c->form[c->cur] == kPost;
-    double *res = c->d_partials + 4 * kMaxPartials;
-    HIP_OR_FAIL(c, launch_residual(c->prec, pull, c->f[c->cur], c->form[p] == kPost, c->f[p],
-                                   c->d_partials, res, c->G, c->Kd, c->Kf, c->H, c->stream));
-    HIP_OR_FAIL(c, launch_sums(c->prec, pull, c->f[c->cur], c->d_partials, res + 4, c->G, c->Kd,
-                               c->Kf, c->H, c->stream));
+    double *res = c->d_partials + kResults;
+    HIP_OR_FAIL(c, launch_check(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
+                                c->form[p] == kPost, c->f[p], c->d_partials, res, c->G, c->Kd,
+                                c->Kf, c->H, c->stream));
     HIP_OR_FAIL(c, hipMemcpyAsync(c->h_check, res, 8 * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
     HIP_OR_FAIL(c, hipEventRecord(c->check_ev, c->stream));

@@ -161,7 +161,6 @@ hipError_t launch_stress(int prec, bool pull, const void *src, const double *rho
 hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, double *out,
                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
                        const HostSide &H, hipStream_t st);
-// out[0] = sum |u_cur - u_prev|^2, out[1] = sum |u_cur|^2, out[3] = NaN/Inf flag
 // batched step over the tile list (count in *ntiles, device memory) on a
 // persistent grid of `workgroups`; case c reads buf[cur ^ flip] and is in pull
 // form when force_pull or its own flag says so
@@ -185,9 +184,16 @@ hipError_t launch_batch_residual(int prec, const void *buf0, const void *buf1,
                                  const Consts<double> *Kd, const HostSide *H, double *partials,
                                  const int *case_first, const int *case_count, int ncases,
                                  double *out, hipStream_t st);
+// out[0] = sum |u_cur - u_prev|^2, out[1] = sum |u_cur|^2, out[3] = NaN/Inf flag
 hipError_t launch_residual(int prec, bool pull_cur, const void *cur, bool pull_prev,
                            const void *prev, double *partials, double *out, const Geometry &G,
                            const Consts<double> &Kd, const Consts<float> &Kf, const HostSide &H,
                            hipStream_t st);
+// out[0..3] as launch_residual and out[4..7] as launch_sums (of cur), in one
+// pass; partials holds 8 values per block (8 * kMaxPartials)
+hipError_t launch_check(int prec, bool pull_cur, const void *cur, bool pull_prev,
+                        const void *prev, double *partials, double *out, const Geometry &G,
+                        const Consts<double> &Kd, const Consts<float> &Kf, const HostSide &H,
+                        hipStream_t st);
 
 }  // namespace lbm

@@ -1227,23 +1227,37 @@ __global__ void stress_kernel(const S *__restrict__ src, const double *__restric
 
 // ------------------------------------------------------------ reductions
 
-// Deterministic FP64 block sum of 4 values: wavefront shuffle tree, then
+// Deterministic FP64 block sum of N values: wavefront shuffle tree, then
 // the wavefront totals in a fixed order.
-__device__ __forceinline__ void block_sum4(double (&v)[4], double *out) {
-    __shared__ double part[kReduceBlock / kWave][4];
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *out) {
+    __shared__ double part[kReduceBlock / kWave][N];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < N; ++q)
         for (int off = kWave / 2; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
     if (lane == 0)
-        for (int q = 0; q < 4; ++q) part[w][q] = v[q];
+        for (int q = 0; q < N; ++q) part[w][q] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < N; ++q) {
             double t = 0.0;
             for (int i = 0; i < kReduceBlock / kWave; ++i) t += part[i][q];
             out[q] = t;
         }
+    }
+}
+
+// Column and row of node idx (row-major, nx per row); 32-bit division when
+// the lattice has fewer than 2^32 nodes, which is the uniform case.
+__device__ __forceinline__ void node_xy(long long idx, int nx, bool narrow, int &x, int &j) {
+    if (narrow) {
+        const unsigned u = static_cast<unsigned>(idx), q = u / static_cast<unsigned>(nx);
+        j = static_cast<int>(q);
+        x = static_cast<int>(u - q * static_cast<unsigned>(nx));
+    } else {
+        j = static_cast<int>(idx / nx);
+        x = static_cast<int>(idx - static_cast<long long>(j) * nx);
     }
 }
 
@@ -1253,9 +1267,11 @@ sums_kernel(const S *__restrict__ src, double *__restrict__ partials, const Geom
             const Consts<double> K, const HostSide H) {
     const long long n = static_cast<long long>(G.nx) * G.ny;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool narrow = n <= 0xffffffffLL;
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        int x, j;
+        node_xy(idx, G.nx, narrow, x, j);
         if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) continue;  // fluid only
         double f9[9], r, vx, vy;
         load_node<S, double, PULL>(src, G, K, row_info(j, G), col_info(x, G), f9);
@@ -1265,7 +1281,7 @@ sums_kernel(const S *__restrict__ src, double *__restrict__ partials, const Geom
         acc[2] += r * vy;
         if (!isfinite(r) || !isfinite(vx) || !isfinite(vy)) acc[3] = 1.0;
     }
-    block_sum4(acc, partials + 4 * blockIdx.x);
+    block_sum(acc, partials + 4 * blockIdx.x);
 }
 
 template <typename SC, typename SP, bool PC, bool PP>
@@ -1275,9 +1291,11 @@ residual_kernel(const SC *__restrict__ cur, const SP *__restrict__ prev,
                 const HostSide H) {
     const long long n = static_cast<long long>(G.nx) * G.ny;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool narrow = n <= 0xffffffffLL;
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const int x = static_cast<int>(idx % G.nx), j = static_cast<int>(idx / G.nx);
+        int x, j;
+        node_xy(idx, G.nx, narrow, x, j);
         if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) continue;  // fluid only
         const RowInfo ri = row_info(j, G);
         const ColInfo ci = col_info(x, G);
@@ -1291,21 +1309,62 @@ residual_kernel(const SC *__restrict__ cur, const SP *__restrict__ prev,
         acc[1] += vx * vx + vy * vy;
         if (!isfinite(vx) || !isfinite(vy) || !isfinite(wx) || !isfinite(wy)) acc[3] = 1.0;
     }
-    block_sum4(acc, partials + 4 * blockIdx.x);
+    block_sum(acc, partials + 4 * blockIdx.x);
 }
 
-// sums the per-block partials in a fixed order; NaN flags are or-ed (max)
+// The residual and the conservation sums of one time level in one pass over
+// the two buffers: values 0..3 accumulate as in residual_kernel, 4..7 as in
+// sums_kernel, node by node in the same order, so each total is the one the
+// separate kernels give.
+template <typename S, bool PC, bool PP>
+__global__ void __launch_bounds__(kReduceBlock)
+check_kernel(const S *__restrict__ cur, const S *__restrict__ prev,
+             double *__restrict__ partials, const Geometry G, const Consts<double> K,
+             const HostSide H) {
+    const long long n = static_cast<long long>(G.nx) * G.ny;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool narrow = n <= 0xffffffffLL;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < n;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        int x, j;
+        node_xy(idx, G.nx, narrow, x, j);
+        if (G.mask && G.mask[static_cast<long long>(j) * G.pitch + x]) continue;  // fluid only
+        const RowInfo ri = row_info(j, G);
+        const ColInfo ci = col_info(x, G);
+        double f9[9], r, vx, vy, r0, wx, wy;
+        load_node<S, double, PC>(cur, G, K, ri, ci, f9);
+        macro_of(f9, H, r, vx, vy);
+        load_node<S, double, PP>(prev, G, K, ri, ci, f9);
+        macro_of(f9, H, r0, wx, wy);
+        const double dx = vx - wx, dy = vy - wy;
+        acc[0] += dx * dx + dy * dy;
+        acc[1] += vx * vx + vy * vy;
+        if (!isfinite(vx) || !isfinite(vy) || !isfinite(wx) || !isfinite(wy)) acc[3] = 1.0;
+        acc[4] += r;
+        acc[5] += r * vx;
+        acc[6] += r * vy;
+        if (!isfinite(r) || !isfinite(vx) || !isfinite(vy)) acc[7] = 1.0;
+    }
+    block_sum(acc, partials + 8 * blockIdx.x);
+}
+
+// sums the per-block partials (N per block) in a fixed order; the NaN flags
+// (every fourth value) are or-ed (max)
+template <int N>
 __global__ void __launch_bounds__(kReduceBlock)
 finalize_kernel(const double *__restrict__ partials, int nparts, double *__restrict__ out) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc[q] = 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        acc[0] += partials[4 * i + 0];
-        acc[1] += partials[4 * i + 1];
-        acc[2] += partials[4 * i + 2];
-        acc[3] = fmax(acc[3], partials[4 * i + 3]);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const double v = partials[N * i + q];
+            acc[q] = (q & 3) == 3 ? fmax(acc[q], v) : acc[q] + v;
+        }
     }
     // flag: any non-zero survives the sum as non-zero
-    block_sum4(acc, out);
+    block_sum(acc, out);
 }
 
 // Batched residual: one workgroup per reduction item (a run of nodes of one
@@ -1354,7 +1413,7 @@ batch_residual_kernel(const S *__restrict__ buf0, const S *__restrict__ buf1,
     case 2: batch_residual_item<S, false, true>(cur, prev, G, K, H, it.start, it.count, acc); break;
     default: batch_residual_item<S, true, true>(cur, prev, G, K, H, it.start, it.count, acc); break;
     }
-    block_sum4(acc, partials + 4 * blockIdx.x);
+    block_sum(acc, partials + 4 * blockIdx.x);
 }
 
 // out[4 c ..] = fixed-order sum of the partials of items first[c] .. first[c] + count[c] - 1
@@ -1371,7 +1430,7 @@ batch_finalize_kernel(const double *__restrict__ partials, const int *__restrict
         acc[2] += p[2];
         acc[3] = fmax(acc[3], p[3]);
     }
-    block_sum4(acc, out + 4 * c);
+    block_sum(acc, out + 4 * c);
 }
 
 hipError_t launch_batch_residual(int prec, const void *b0, const void *b1,
@@ -1520,7 +1579,7 @@ hipError_t launch_sums(int prec, bool pull, const void *src, double *partials, d
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
+    hipLaunchKernelGGL(finalize_kernel<4>, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 
@@ -1548,7 +1607,35 @@ hipError_t launch_residual(int prec, bool pull_cur, const void *cur, bool pull_p
                                   static_cast<const double *>(prev), partials, G, Kd, H, nb, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
+    hipLaunchKernelGGL(finalize_kernel<4>, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
+template <typename S>
+static void check_dispatch(bool pc, const S *cur, bool pp, const S *prev, double *partials,
+                           const Geometry &G, const Consts<double> &Kd, const HostSide &H, int nb,
+                           hipStream_t st) {
+    const dim3 grid(nb), block(kReduceBlock);
+    if (pc && pp) hipLaunchKernelGGL((check_kernel<S, true, true>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+    else if (pc) hipLaunchKernelGGL((check_kernel<S, true, false>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+    else if (pp) hipLaunchKernelGGL((check_kernel<S, false, true>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+    else hipLaunchKernelGGL((check_kernel<S, false, false>), grid, block, 0, st, cur, prev, partials, G, Kd, H);
+}
+
+hipError_t launch_check(int prec, bool pull_cur, const void *cur, bool pull_prev,
+                        const void *prev, double *partials, double *out, const Geometry &G,
+                        const Consts<double> &Kd, const Consts<float> &, const HostSide &H,
+                        hipStream_t st) {
+    const int nb = reduce_blocks(G);
+    if (f32_storage(prec))
+        check_dispatch<float>(pull_cur, static_cast<const float *>(cur), pull_prev,
+                              static_cast<const float *>(prev), partials, G, Kd, H, nb, st);
+    else
+        check_dispatch<double>(pull_cur, static_cast<const double *>(cur), pull_prev,
+                               static_cast<const double *>(prev), partials, G, Kd, H, nb, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel<8>, dim3(1), dim3(kReduceBlock), 0, st, partials, nb, out);
     return hipGetLastError();
 }
 
