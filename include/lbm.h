@@ -166,7 +166,8 @@ int lbm_sums(lbm_ctx *ctx, double out[3]);
  * and a copy of their results to pinned host memory the context owns, and
  * returns; check_result waits only for the latest enqueued check (the steps
  * enqueued after it keep the GPU busy) and returns R, sums[0..2] and the step
- * count at which it was taken.  A later check_async replaces the pending one.
+ * count at which it was taken.  A later check_async replaces the pending one;
+ * one that fails leaves none pending.
  * R, sums and step may be NULL.
  * Errors: check_async: LBM_E_STATE before the first step (as lbm_residual),
  * LBM_E_NOMEM (pinned buffer), LBM_E_DEVICE.  check_result: LBM_E_STATE if no

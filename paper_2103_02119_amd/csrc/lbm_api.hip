@@ -545,6 +545,7 @@ extern "C" int lbm_check_async(lbm_ctx *c) {
     }
     const int p = 1 - c->cur;
     double *res = c->d_partials + kResults;
+    c->check_step = -1;  // nothing to read if an enqueue below fails
     HIP_OR_FAIL(c, launch_check(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
                                 c->form[p] == kPost, c->f[p], c->d_partials, res, c->G, c->Kd,
                                 c->Kf, c->H, c->stream));
