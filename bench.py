@@ -400,6 +400,8 @@ def main():
             "storage": "FP32 deviations f - w rho0" if prec == L.LBM_FP32_DEV else "FP64",
             "cs2": info["cs2"], "tau": round(info["tau"], 6),
             "residual_every": args.check_every,
+            "residual_read": "asynchronous, one interval later",
+            "launches_per_host_call": args.chunk,
             "rows_per_wave": rows, "workgroups": wgs,
         },
         "roofline": {
