@@ -231,7 +231,13 @@ def test_async_check_matches_the_synchronous_reductions(prec):
         with pytest.raises(L.LbmError) as e:
             call()
         assert e.value.code == L.LBM_E_STATE
-    lat.step(7)
+    lat.step(1)  # the current level pulled, the earlier one as set (mixed forms)
+    R1, S1 = lat.residual(), lat.sums()
+    lat.check_async()
+    R, S, step = lat.check_result()
+    assert R == pytest.approx(R1, rel=1e-13)
+    assert np.abs(S - S1).max() <= 1e-13 * S1[0]
+    lat.step(6)
     at = lat.steps_done
     R7, S7 = lat.residual(), lat.sums()
     lat.check_async()
