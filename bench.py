@@ -198,7 +198,9 @@ def time_to_steady(name, tol=1e-8, check_every=1000, cap=2_000_000):
     lat.close()
     return dict(cold_steps=steps if R <= tol else None, cold_seconds=round(wall, 3),
                 residual=R, tol=tol, precision="fp64", collision="RC",
-                checked_every=check_every, warm_steps=None, warm_seconds=None)
+                checked_every=check_every, warm_steps=None, warm_seconds=None,
+                warm_start="not on this lattice: the network is trained on 256x128 cavities "
+                           "with obstacles (python -m paper_2103_02119_amd.warmstart)")
 
 
 def bench_sweep(args):
