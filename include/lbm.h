@@ -123,9 +123,31 @@ int lbm_create(int nx, int ny, double r, const double rates[9], const lbm_bc *bc
 int lbm_set_fields(lbm_ctx *ctx, const double *rho, const double *ux, const double *uy);
 
 /* Enqueues n >= 0 collide-and-stream steps on the stream (Sec. 3 / Sec. 4
- * algorithm, one fused kernel per step) and returns without waiting.
+ * algorithm: pull streaming, macroscopic fields, collision; each launch
+ * fuses one step, or two steps with the intermediate state kept on chip, see
+ * lbm_set_steps_per_launch) and returns without waiting.  Under the automatic
+ * choice the call's last launch advances one step, so lbm_residual of the
+ * last step is always available afterwards.
  * Errors: LBM_E_INVAL for n < 0; LBM_E_DEVICE if a launch fails. */
 int lbm_step(lbm_ctx *ctx, long n);
+
+/* Steps fused into one launch by later lbm_step calls: 1, 2 or 0 (automatic,
+ * the default).  Two steps per launch (temporal blocking) read the state of
+ * step t-1 once, keep each tile's step-t state in on-chip memory and write
+ * step t+1, halving the population traffic per step; results are bit-identical
+ * to one step per launch.  They apply only without an obstacle mask (with a
+ * mask every launch advances one step).  Automatic: two once the two
+ * population buffers exceed the GPU's 256 MB Infinity Cache, one below.  With
+ * an explicit 2 an lbm_step call advances pairs of steps while two remain, so
+ * after an even count the state one step back is not held and lbm_residual /
+ * lbm_check_async return LBM_E_STATE until a one-step launch
+ * (an odd count, or lbm_step(ctx, 1)).
+ * Errors: LBM_E_INVAL (ctx NULL, k not 0, 1 or 2). */
+int lbm_set_steps_per_launch(lbm_ctx *ctx, int k);
+
+/* Steps per launch that lbm_step currently takes for a long run (1 or 2),
+ * after the automatic choice and the mask rule; LBM_E_INVAL for a NULL ctx. */
+int lbm_steps_per_launch(const lbm_ctx *ctx);
 
 /* Macroscopic fields at the current time level: rho = sum f,
  * u = (sum f e + F/2) / rho (Sec. 3, "update hydrodynamic fields"), written
@@ -137,8 +159,9 @@ int lbm_moments(lbm_ctx *ctx, double *rho, double *ux, double *uy);
  * R = sqrt(sum |u^n - u^{n-1}|^2) / sqrt(sum |u^n|^2), summed in FP64 over all
  * fluid nodes with a deterministic two-pass reduction.  Synchronizes.
  * Errors: LBM_E_STATE before the first step (or after set_fields /
- * set_populations); LBM_E_UNSTABLE if any velocity is NaN or Inf (*R is then
- * NaN); LBM_E_DEVICE. */
+ * set_populations, or when the last launch advanced two steps under an
+ * explicit lbm_set_steps_per_launch(ctx, 2)); LBM_E_UNSTABLE if any velocity
+ * is NaN or Inf (*R is then NaN); LBM_E_DEVICE. */
 int lbm_residual(lbm_ctx *ctx, double *R);
 
 /* Local viscous stress at the current time level, computed in FP64 from the
@@ -221,6 +244,17 @@ int lbm_smooth_step(lbm_ctx *ctx);
  * following steps; the state is kept.  Synchronizes.
  * Errors: LBM_E_INVAL (a rate outside (0, 2)), LBM_E_DEVICE. */
 int lbm_set_rates(lbm_ctx *ctx, const double rates[9]);
+
+/* Streaming copy of `bytes` bytes from src to dst (device pointers, both
+ * 16-byte aligned, bytes a multiple of 16) by the library's own kernel:
+ * 16-byte loads and non-temporal 16-byte stores, grid-stride over
+ * `workgroups` workgroups of 256 threads (0 = 8192).  It measures the
+ * bandwidth that a plain read-plus-write stream reaches on this GPU, the
+ * ceiling the step kernels are compared with.  Enqueues on `stream`
+ * (hipStream_t, NULL = null stream) and returns without waiting.
+ * Errors (text in lbm_last_error(NULL)): LBM_E_INVAL (NULL pointer,
+ * misalignment, workgroups < 0), LBM_E_DEVICE. */
+int lbm_stream_copy(void *dst, const void *src, size_t bytes, int workgroups, void *stream);
 
 /* Number of steps taken since creation (set_fields / set_populations do not
  * reset it). */

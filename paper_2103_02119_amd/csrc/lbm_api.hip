@@ -27,6 +27,7 @@ enum Form { kEmpty = 0, kPre = 1, kPost = 2 };
 // reduction partials (up to 8 values per block), then the results
 static constexpr size_t kResults = 8 * static_cast<size_t>(kMaxPartials);
 
+
 struct lbm_ctx {
     int nx, ny;
     double a;
@@ -54,6 +55,7 @@ struct lbm_ctx {
     size_t stage_bytes;
     unsigned char *d_mask;        // obstacle mask [ny][pitch] (or null)
     unsigned char *d_tile_solid;  // per step tile: obstacle in its neighbourhood
+    int steps_per_launch;         // 0 automatic, 1, 2 (lbm_set_steps_per_launch)
     long steps;
     char err[512];
 };
@@ -424,21 +426,66 @@ extern "C" int lbm_set_fields(lbm_ctx *c, const double *rho, const double *ux, c
     return LBM_OK;
 }
 
+// Steps per launch a run takes: two (the temporally blocked kernel) where
+// the tile kernel applies (no obstacle mask) and the caller asked for it or,
+// automatically, once the two population buffers exceed the 256 MB Infinity
+// Cache, so that a step is bound by HBM traffic; one otherwise.
+static int steps_per_launch(const lbm_ctx *c) {
+    if (!uses_tile_kernel(c->G) || c->steps_per_launch == 1) return 1;
+    if (c->steps_per_launch == 2) return 2;
+    return c->G.nt_store ? 2 : 1;
+}
+
 extern "C" int lbm_step(lbm_ctx *c, long n) {
     if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
     if (n < 0) return fail_ctx(c, LBM_E_INVAL, "n must be >= 0");
-    for (long i = 0; i < n; ++i) {
+    const int k = steps_per_launch(c);
+    // With two steps per launch the state before the last step is not kept.
+    // The automatic choice ends every call with a one-step launch, so that
+    // the residual of the last step stays available; an explicit 2 takes
+    // pairs as long as two steps remain.
+    const long last_single = c->steps_per_launch == 2 ? 1 : 2;
+    for (long left = n; left > 0;) {
         const int src = c->cur, dst = 1 - c->cur;
         const bool pull = c->form[src] == kPost;
-        hipError_t e = launch_step(c->prec, c->coll, pull, c->higher_unit, c->f[src], c->f[dst],
-                                   c->G, c->Kd, c->Kf, c->stream);
+        const bool two = k == 2 && pull && left > last_single;
+        hipError_t e = two ? launch_step2(c->prec, c->coll, c->higher_unit, c->f[src], c->f[dst],
+                                          c->G, c->Kd, c->Kf, c->stream)
+                           : launch_step(c->prec, c->coll, pull, c->higher_unit, c->f[src],
+                                         c->f[dst], c->G, c->Kd, c->Kf, c->stream);
         if (e != hipSuccess)
             return fail_ctx(c, LBM_E_DEVICE, "step kernel launch failed: %s", hipGetErrorString(e));
         c->form[dst] = kPost;
         c->cur = dst;
-        c->prev_valid = 1;
-        ++c->steps;
+        c->prev_valid = two ? 0 : 1;
+        c->steps += two ? 2 : 1;
+        left -= two ? 2 : 1;
     }
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_steps_per_launch(lbm_ctx *c, int k) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (k < 0 || k > 2) return fail_ctx(c, LBM_E_INVAL, "steps per launch must be 0, 1 or 2");
+    c->steps_per_launch = k;
+    return LBM_OK;
+}
+
+extern "C" int lbm_steps_per_launch(const lbm_ctx *c) {
+    if (!c) return LBM_E_INVAL;
+    return steps_per_launch(c);
+}
+
+extern "C" int lbm_stream_copy(void *dst, const void *src, size_t bytes, int workgroups,
+                               void *stream) {
+    if (!dst || !src) return fail_ctx(nullptr, LBM_E_INVAL, "NULL buffer");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+        return fail_ctx(nullptr, LBM_E_INVAL, "buffers and size must be multiples of 16 bytes");
+    if (workgroups < 0) return fail_ctx(nullptr, LBM_E_INVAL, "workgroups must be >= 0");
+    hipError_t e = launch_stream_copy(dst, src, static_cast<long long>(bytes / 16), workgroups,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_ctx(nullptr, LBM_E_DEVICE, "copy kernel launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
 
@@ -505,7 +552,7 @@ extern "C" int lbm_sums(lbm_ctx *c, double out[3]) {
 extern "C" int lbm_residual(lbm_ctx *c, double *R) {
     if (!c || !R) return fail_ctx(c, LBM_E_INVAL, "NULL argument");
     if (!c->prev_valid || c->form[1 - c->cur] == kEmpty)
-        return fail_ctx(c, LBM_E_STATE, "no step taken since the state was set");
+        return fail_ctx(c, LBM_E_STATE, "the state one step before the current one is not held");
     const int p = 1 - c->cur;
     HIP_OR_FAIL(c, launch_residual(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
                                    c->form[p] == kPost, c->f[p], c->d_partials,
@@ -530,7 +577,7 @@ extern "C" int lbm_residual(lbm_ctx *c, double *R) {
 extern "C" int lbm_check_async(lbm_ctx *c) {
     if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
     if (!c->prev_valid || c->form[1 - c->cur] == kEmpty)
-        return fail_ctx(c, LBM_E_STATE, "no step taken since the state was set");
+        return fail_ctx(c, LBM_E_STATE, "the state one step before the current one is not held");
     if (!c->h_check) {
         void *h = nullptr;
         if (hipHostMalloc(&h, 8 * sizeof(double)) != hipSuccess || !h)

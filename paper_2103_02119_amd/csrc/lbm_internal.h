@@ -130,7 +130,7 @@ int pitch_of(int nx);
 const char *create_error_text();
 int set_create_error(const char *msg);
 
-// ---- launchers implemented in lbm_kernels.hip (return hipError_t) ----
+// ---- launchers implemented in the kernel sources (return hipError_t) ----
 // workgroups of the tile kernel for a lattice (whole groups of 8)
 int tile_workgroups(const Geometry &G);
 // the step kernel a launch takes: the tile kernel unless tile_rows is 0 or a mask is set
@@ -138,6 +138,22 @@ inline bool uses_tile_kernel(const Geometry &G) { return G.tile_rows > 0 && !G.m
 hipError_t launch_step(int prec, int coll, bool pull, bool higher_unit, const void *src, void *dst,
                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
                        hipStream_t st);
+// the march step kernel (lbm_march.hip); launch_step takes it when the tile
+// kernel does not apply
+hipError_t launch_march_step(int prec, int coll, bool pull, bool higher_unit, const void *src,
+                             void *dst, const Geometry &G, const Consts<double> &Kd,
+                             const Consts<float> &Kf, hipStream_t st);
+// two steps per launch (lbm_tile2.hip): src must hold post-collision values
+// (pull form) and the lattice no obstacle mask; dst receives step t+1
+hipError_t launch_step2(int prec, int coll, bool higher_unit, const void *src, void *dst,
+                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
+                        hipStream_t st);
+// streaming copy of n16 16-byte words (the measured bandwidth ceiling);
+// workgroups <= 0 selects the default grid
+hipError_t launch_stream_copy(void *dst, const void *src, long long n16, int workgroups,
+                              hipStream_t st);
+// workgroups (= partial sums) of the reductions on a lattice (<= kMaxPartials)
+int reduce_partials(const Geometry &G);
 hipError_t launch_init_feq(int prec, void *dst, const double *rho, const double *ux,
                            const double *uy, const Geometry &G, const HostSide &H, hipStream_t st);
 hipError_t launch_set_populations(int prec, void *dst, const double *f, const Geometry &G,

@@ -26,10 +26,12 @@ LBM_RC, LBM_RNR = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
+           "lbm_set_steps_per_launch", "lbm_steps_per_launch",
            "lbm_moments", "lbm_stress", "lbm_residual", "lbm_sums", "lbm_check_async",
-           "lbm_check_result", "lbm_get_populations", "lbm_set_populations", "lbm_set_mask",
-           "lbm_set_rates", "lbm_set_force", "lbm_step_forced", "lbm_smooth_step",
-           "lbm_steps_done", "lbm_launch_shape", "lbm_last_error", "lbm_destroy")
+           "lbm_check_result", "lbm_get_populations", "lbm_set_populations",
+           "lbm_set_mask", "lbm_set_rates", "lbm_set_force", "lbm_step_forced", "lbm_smooth_step",
+           "lbm_stream_copy", "lbm_steps_done", "lbm_launch_shape", "lbm_last_error",
+           "lbm_destroy")
 BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fields",
                  "lbm_batch_set_mask", "lbm_batch_set_rates", "lbm_batch_smooth_step",
                  "lbm_batch_set_active", "lbm_batch_step", "lbm_batch_residuals",
@@ -121,6 +123,13 @@ def load():
                              ctypes.POINTER(_CTX)]
     L.lbm_set_fields.argtypes = [_CTX, _D, _D, _D]
     L.lbm_step.argtypes = [_CTX, ctypes.c_long]
+    L.lbm_set_steps_per_launch.argtypes = [_CTX, ctypes.c_int]
+    L.lbm_set_steps_per_launch.restype = ctypes.c_int
+    L.lbm_steps_per_launch.argtypes = [_CTX]
+    L.lbm_steps_per_launch.restype = ctypes.c_int
+    L.lbm_stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                  ctypes.c_void_p]
+    L.lbm_stream_copy.restype = ctypes.c_int
     L.lbm_moments.argtypes = [_CTX, _D, _D, _D]
     L.lbm_stress.argtypes = [_CTX, _D, _D, _D]
     L.lbm_residual.argtypes = [_CTX, _D]
@@ -249,6 +258,17 @@ def lbm_step(ctx, n: int):
     _check(load().lbm_step(ctx, int(n)), ctx)
 
 
+def lbm_set_steps_per_launch(ctx, k: int):
+    _check(load().lbm_set_steps_per_launch(ctx, int(k)), ctx)
+
+
+def lbm_steps_per_launch(ctx) -> int:
+    k = load().lbm_steps_per_launch(ctx)
+    if k < 0:
+        raise LbmError(k, "NULL context")
+    return k
+
+
 def lbm_moments(ctx, nx, ny):
     rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
     _check(load().lbm_moments(ctx, rho.ctypes.data_as(_D), ux.ctypes.data_as(_D),
@@ -285,6 +305,13 @@ def lbm_check_result(ctx):
     _check(load().lbm_check_result(ctx, ctypes.byref(R), out.ctypes.data_as(_D),
                                    ctypes.byref(step)), ctx)
     return R.value, out, step.value
+
+
+def lbm_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, workgroups: int = 0, stream=None):
+    """The library's streaming copy kernel between two device buffers."""
+    _check(load().lbm_stream_copy(ctypes.c_void_p(int(dst_ptr)), ctypes.c_void_p(int(src_ptr)),
+                                  int(nbytes), int(workgroups),
+                                  None if stream is None else ctypes.c_void_p(int(stream))), None)
 
 
 def lbm_get_populations(ctx, nx, ny):
@@ -390,6 +417,12 @@ class Lattice:
 
     def step(self, n=1):
         lbm_step(self.ctx, n)
+
+    def set_steps_per_launch(self, k):
+        lbm_set_steps_per_launch(self.ctx, k)
+
+    def steps_per_launch(self):
+        return lbm_steps_per_launch(self.ctx)
 
     def moments(self):
         return lbm_moments(self.ctx, self.nx, self.ny)

@@ -211,9 +211,25 @@ def test_null_handles_are_rejected_before_touching_the_device():
         "lbm_set_force": (None, 0.0, 0.0),
         "lbm_step_forced": (None, 1, pd, pd),
         "lbm_smooth_step": (None,),
+        "lbm_set_steps_per_launch": (None, 1),
     }
     for name, args in calls.items():
         assert getattr(lib, name)(*args) == L.LBM_E_INVAL, name
+    assert lib.lbm_steps_per_launch(None) == L.LBM_E_INVAL
     assert lib.lbm_destroy(None) == L.LBM_OK
     assert lib.lbm_batch_step(None, 1) == L.LBM_E_INVAL
     assert lib.lbm_batch_destroy(None) == L.LBM_OK
+
+
+def test_stream_copy_validates_before_touching_the_device():
+    lib = L.load()
+    assert lib.lbm_stream_copy(None, ctypes.c_void_p(0x1000), 16, 0, None) == L.LBM_E_INVAL
+    assert lib.lbm_stream_copy(ctypes.c_void_p(0x1000), None, 16, 0, None) == L.LBM_E_INVAL
+    # sizes and addresses must be multiples of 16 bytes
+    assert lib.lbm_stream_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 24, 0,
+                               None) == L.LBM_E_INVAL
+    assert lib.lbm_stream_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 32, 0,
+                               None) == L.LBM_E_INVAL
+    assert lib.lbm_stream_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 32, -1,
+                               None) == L.LBM_E_INVAL
+    assert "16 bytes" in L.lbm_last_error(None) or "workgroups" in L.lbm_last_error(None)

@@ -123,3 +123,18 @@ def test_taylor_green_decay_at_full_size(prec):
     print("decay rate / 2 nu k^2 =", rate / (2 * nu * k * k), flush=True)
     assert abs(rate / (2 * nu * k * k) - 1) < 1e-2
     lat.close()
+
+
+def test_stream_copy_kernel_copies_every_byte():
+    """The library's copy kernel (the bandwidth reference of the benchmark)
+    moves every byte, including a tail shorter than one round of the grid."""
+    import torch
+
+    for nbytes in (16, 4096 * 16 + 48, (64 << 20) + 16 * 1234):
+        print(f"case: stream copy {nbytes} bytes", flush=True)
+        a = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+        b = torch.zeros_like(a)
+        L.lbm_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, 0,
+                          torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
