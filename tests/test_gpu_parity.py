@@ -338,7 +338,7 @@ def _oracle_rounding_floor(make_p, f_init, nsteps, lams=(3.0, 0.7, 5.0, 1.3, 0.3
 
 
 @pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
-def test_poiseuille_32x16_20000_steps(coll):
+def test_poiseuille_32x16_20000_steps(coll, record_property):
     """nx 32, ny 16, a 0.5, nu 0.1, Fx 1e-6: u is ~8e-5, so an FP64 rounding
     difference of one ulp of the O(0.1) populations is ~2e-12 of max |u|.
     Populations must agree to 1e-12; the velocity to 1e-12 or, if larger,
@@ -362,8 +362,12 @@ def test_poiseuille_32x16_20000_steps(coll):
     r_o, ux_o, uy_o = O.moments(p, ref)
     r_g, ux_g, uy_g = lat.moments()
     floor = _oracle_rounding_floor(make_p, lambda q: O.init(make_p()), 20000)
-    print("oracle rounding floor on u:", floor, "gpu vs oracle:", rel(ux_g, ux_o), flush=True)
-    assert rel(ux_g, ux_o) < max(TOL64, 3 * floor)
+    err = rel(ux_g, ux_o)
+    print("oracle rounding floor on u:", floor, "gpu vs oracle:", err, flush=True)
+    record_property("gpu_vs_oracle_ux", err)
+    record_property("oracle_rounding_floor_ux", floor)
+    assert err < max(TOL64, 3 * floor), (
+        f"GPU vs oracle u_x {err:.3e}; oracle rounding floor {floor:.3e}")
     assert np.abs(uy_g).max() < 1e-14 and np.abs(uy_o).max() < 1e-14  # zero up to rounding
     assert rel(r_g, r_o) < TOL64
     H = ny * a
