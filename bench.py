@@ -1,26 +1,33 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the fused rectangular-lattice CM-LBM step on one GPU.
 
-Default workload: lid-driven cavity on a square physical domain, nx 512 x
-ny 1024 nodes at aspect ratio r = dy/dx = 0.5, Re 1000, lid speed 0.05,
-FP32-deviation storage, RC collision (the raw-moment RNR variant is timed
-beside it).  A step is one collide-and-stream pass over the whole lattice;
-every `--check-every` steps the FP64 residual and conservation reductions run
-inside the timed region, as in a run to steady state (enqueued without a host
-wait and read one interval later, as a monitored production run would).  Inputs (the cavity at
-rest, after the warm-up steps) are resident in HBM when timing starts.
+Default workload: the doubly periodic shear layer on nx 2048 x ny 8192 nodes
+at aspect ratio r = dy/dx = 0.25 (kappa 80, delta 0.05, u0 0.04), FP32
+deviation storage, RC collision.  Its two population buffers (1.2 GB) are far
+beyond the 256 MB Infinity Cache, so the step is bound by HBM: this is the
+roofline workload.  A step is one collide-and-stream pass over the whole
+lattice.  The timed region runs `--steps` steps in chunks of `--chunk`; every
+chunk's launches fuse two steps each except the last one or two, which fuse
+one, and every `--check-every` steps and at the end of the timed region the
+FP64 residual and conservation reductions run (enqueued without a host wait;
+the last one is read before the clock stops).  Inputs (the shear layer after
+the warm-up steps) are resident in HBM when timing starts.
 
-Prints ONE JSON line: MLUPS of the whole job, the roofline of the step kernel
-(algorithmic bytes per launch / mean launch time from HIP events on the
-library's stream), the HBM traffic measured by rocprofv3 counters (when
-profiles/ holds a measurement of the current kernel source) and the CPU
-oracle timed on a bounded sample on the host.  On the cavity it also times
-a cold start to a residual of 1e-8 (in FP64).
+Beside the headline it reports: the library's own streaming copy of one
+population buffer (the copy ceiling), the one-step-per-launch kernel, the
+same workload in FP64 and with the raw-moment (RNR) collision, the
+cache-resident 512 x 1024 cavity, time to steady state, and the FP64 CPU
+oracle timed on a bounded sample on the host.
+
+Prints ONE JSON line.  The roofline is that of the dominant kernel: its
+algorithmic bytes per launch (9 reads + 9 writes per node) over its mean
+launch time from HIP events on the library's stream inside the timed region.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -30,11 +37,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2103_02119_amd", "csrc", "lbm_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2103_02119_amd", "csrc")
+KERNEL_SRCS = ("lbm_device.h", "lbm_tile.hip", "lbm_tile2.hip", "lbm_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+METRIC = "MLUPS + % HBM roofline; time-to-steady-state warm-start vs cold"
 
 WORKLOADS = {
-    # name: nx, ny, r, cs2, bc types, wall velocities, Re, lid/velocity scale
+    # name: nx, ny, r, cs2, bc types, wall velocities, Re or nu, velocity scale
     "cavity": dict(nx=512, ny=1024, r=0.5, cs2=0.16, bc=(1, 1, 1, 2), U=0.05, Re=1000.0),
     "tgv": dict(nx=1024, ny=2048, r=0.5, cs2=0.16, bc=(0, 0, 0, 0), U=0.02, nu=0.1),
     # the shear layer's own nu = 1e-4 (tau = 0.5025) is below the scheme's
@@ -43,55 +52,88 @@ WORKLOADS = {
     # stays finite for 30 000 steps (the step's cost does not depend on nu)
     "shear": dict(nx=2048, ny=8192, r=0.25, cs2=0.04, bc=(0, 0, 0, 0), U=0.04, nu=6e-3),
 }
+# 80% of the 8 TB/s HBM roofline at the one-step traffic of 72 B (FP32
+# deviations) or 144 B (FP64) per lattice update, in MLUPS
+TARGET_MLUPS = {"fp32dev": 0.8 * HBM_PEAK_GBS * 1e9 / 72 / 1e6,
+                "fp64": 0.8 * HBM_PEAK_GBS * 1e9 / 144 / 1e6}
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SRCS:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def setup(name, precision, collision, rows=0):
-    from paper_2103_02119_amd import inputs as I
-    from paper_2103_02119_amd import lbm as L
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
+
+def params_of(name):
     w = WORKLOADS[name]
     nx, ny, r, cs2 = w["nx"], w["ny"], w["r"], w["cs2"]
     nu = w["U"] * nx / w["Re"] if "Re" in w else w["nu"]
     tau = nu / cs2 + 0.5
     rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
     uw = ((0, 0), (0, 0), (0, 0), (w["U"], 0)) if name == "cavity" else ((0, 0),) * 4
-    lat = L.Lattice(nx, ny, r, rates, bc_types=w["bc"], u_wall=uw, cs2=cs2,
-                    collision=collision, precision=precision, rows_per_wave=rows)
+    return w, nx, ny, r, cs2, nu, tau, rates, uw
+
+
+def initial_fields(name, nx, ny, r, w, cs2):
+    from paper_2103_02119_amd import inputs as I
     if name == "cavity":
-        lat.set_fields(*I.cavity_rest(nx, ny))
-    elif name == "tgv":
-        lat.set_fields(*I.taylor_green(nx, ny, r, w["U"], cs2))
-    else:
-        lat.set_fields(*I.shear_layer(nx, ny, r, u0=w["U"]))
+        return I.cavity_rest(nx, ny)
+    if name == "tgv":
+        return I.taylor_green(nx, ny, r, w["U"], cs2)
+    return I.shear_layer(nx, ny, r, u0=w["U"])
+
+
+def setup(name, precision, collision):
+    from paper_2103_02119_amd import lbm as L
+
+    w, nx, ny, r, cs2, nu, tau, rates, uw = params_of(name)
+    lat = L.Lattice(nx, ny, r, rates, bc_types=w["bc"], u_wall=uw, cs2=cs2,
+                    collision=collision, precision=precision)
+    lat.set_fields(*initial_fields(name, nx, ny, r, w, cs2))
     return lat, dict(nx=nx, ny=ny, r=r, cs2=cs2, tau=tau, nu=nu)
 
 
-def time_steps(lat, steps, check_every, chunk):
-    """Times `steps` steps issued `chunk` launches at a time (one C-level
-    loop per chunk), each chunk bracketed by HIP events on torch's current
-    stream (the stream the library enqueues on).  Every `check_every` steps
-    the FP64 residual and conservation reductions are enqueued without a
-    host wait (lbm_check_async), and the previous check's results are read
-    then, one interval later, so the queue never drains; the last one is
-    read before the clock stops.  Returns the wall time, the per-launch
-    kernel times from the events and the step of the first check that
-    reported a non-finite field (None if none did)."""
+def time_steps(lat, steps, check_every, chunk, spl):
+    """Times `steps` steps in chunks of `chunk`.  With two steps per launch
+    (spl = 2) a chunk of c steps is (c - 1) // 2 two-step launches bracketed
+    by HIP events on torch's current stream (the library's stream), then one
+    or two one-step launches, so that the state one step back exists for the
+    check; with spl = 1 the events bracket all c launches.  Every
+    `check_every` steps, and once at the end, the FP64 residual and
+    conservation reductions are enqueued without a host wait
+    (lbm_check_async) and the previous check's results are read then; the
+    last one is read before the clock stops.  Returns the wall time, the mean
+    time of one bracketed launch, the number of checks and the step of the
+    first check that found a non-finite field (None if none did)."""
     import torch
 
     from paper_2103_02119_amd import lbm as L
 
     s = torch.cuda.current_stream()
-    nchunks = (steps + chunk - 1) // chunk
+    lat.set_steps_per_launch(spl)
+    plan = []
+    done = 0
+    while done < steps:
+        c = min(chunk, steps - done)
+        pairs = (c - 1) // 2 if spl == 2 else 0
+        plan.append((c, pairs))
+        done += c
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(nchunks)]
-    sizes = []
-    blew_up = None
-    pending = None  # steps done at the enqueued, unread check
+          for _ in plan]
+    blew_up, pending, checks = None, None, 0
 
     def read():
         nonlocal blew_up
@@ -105,58 +147,194 @@ def time_steps(lat, steps, check_every, chunk):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    for c in range(nchunks):
-        n = min(chunk, steps - done)
-        ev[c][0].record(s)
-        lat.step(n)
-        ev[c][1].record(s)
-        sizes.append(n)
-        done += n
-        if check_every and done % check_every == 0 and blew_up is None:
+    for i, (c, pairs) in enumerate(plan):
+        if spl == 2:
+            ev[i][0].record(s)
+            lat.step(2 * pairs)
+            ev[i][1].record(s)
+            for _ in range(c - 2 * pairs):
+                lat.step(1)
+        else:
+            ev[i][0].record(s)
+            lat.step(c)
+            ev[i][1].record(s)
+        done += c
+        last = i == len(plan) - 1
+        if (last or (check_every and done % check_every == 0)) and blew_up is None:
             if pending is not None:
                 read()
             lat.check_async()
+            checks += 1
             pending = done
     if pending is not None and blew_up is None:
         read()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_launch = [a.elapsed_time(b) / n for (a, b), n in zip(ev, sizes)]
-    return wall, per_launch, blew_up
+    launches = [(a.elapsed_time(b), (p if spl == 2 else c)) for (a, b), (c, p) in zip(ev, plan)]
+    tot_ms = sum(t for t, n in launches if n > 0)
+    tot_n = sum(n for _, n in launches)
+    return wall, (tot_ms / tot_n if tot_n else float("nan")), checks, blew_up
+
+
+def time_launches(lat, spl, n):
+    """Mean time (ms) of n back-to-back launches of spl steps each, from HIP
+    events on the library's stream (outside the timed region)."""
+    import torch
+
+    lat.set_steps_per_launch(spl)
+    if spl == 2:
+        lat.step(1)  # pull form
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    lat.step(spl * n)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def copy_ceiling(nbytes, reps=10):
+    """The library's streaming copy (lbm_stream_copy) of one population
+    buffer's size, best over a few grid sizes: the read-plus-write bandwidth
+    a plain stream reaches on this GPU."""
+    import torch
+
+    from paper_2103_02119_amd import lbm as L
+
+    nbytes = nbytes // 16 * 16
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    best = None
+    per_grid = {}
+    for wgs in (2048, 4096, 8192, 16384, 65536):
+        L.lbm_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, wgs, s.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            L.lbm_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, wgs, s.cuda_stream)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+        per_grid[wgs] = round(gbs, 1)
+        if best is None or gbs > best[0]:
+            best = (gbs, wgs, ms)
+    assert torch.equal(a[:4096], b[:4096])
+    del a, b
+    torch.cuda.empty_cache()
+    return dict(kernel="lbm::stream_copy_kernel (lbm_stream_copy)", bytes_each_way=nbytes,
+                GBs=round(best[0], 1), workgroups=best[1], us=round(1e3 * best[2], 2),
+                per_workgroups_GBs=per_grid)
+
+
+def run_workload(name, prec_name, collision, args, spl=0, one_step=True):
+    """Setup, warm-up and the timed region for one workload; returns a dict."""
+    import torch
+
+    from paper_2103_02119_amd import lbm as L
+
+    prec = L.LBM_FP32_DEV if prec_name == "fp32dev" else L.LBM_FP64
+    lat, info = setup(name, prec, collision)
+    nodes = info["nx"] * info["ny"]
+    k = spl or lat.steps_per_launch()
+    lat.set_steps_per_launch(k)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    wall, kern_ms, checks, blew_up = time_steps(lat, args.steps, args.check_every, args.chunk, k)
+    try:
+        R = lat.residual()
+        sums = lat.sums()
+    except L.LbmError as e:
+        if e.code != L.LBM_E_UNSTABLE:
+            raise
+        R, sums = float("nan"), [float("nan")] * 3
+        blew_up = blew_up or args.warmup + args.steps
+    vb = 4 if prec == L.LBM_FP32_DEV else 8
+    out = dict(nodes=nodes, info=info, wall=wall, steps_per_launch=k, kernel_ms=kern_ms,
+               mlups=nodes * args.steps / wall / 1e6, checks=checks, residual=R, mass=sums[0],
+               nonfinite_at_step=blew_up, value_bytes=vb,
+               bytes_per_launch=18 * vb * nodes)
+    if one_step:
+        out["one_step_ms"] = time_launches(lat, 1, max(args.steps, 10))
+        if k == 1:
+            out["two_step_ms"] = time_launches(lat, 2, max(args.steps // 2, 5))
+    lat.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(r, copy_gbs, traffic=None):
+    bpl = r["bytes_per_launch"]
+    k = r["steps_per_launch"]
+    achieved = bpl / (r["kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic[0] if traffic else None,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_over_algorithmic": traffic[1] if traffic else None,
+        "kernel": "lbm::tile2_step_kernel" if k == 2 else "lbm::tile_step_kernel",
+        "steps_per_launch": k,
+        "algorithmic_bytes_per_launch": bpl,
+        "bytes_per_lu": bpl // (k * r["nodes"]),
+        "kernel_us": round(1e3 * r["kernel_ms"], 3),
+        "kernel_time_from": "HIP events on the library's stream around the timed region's "
+                            + ("two-step launches" if k == 2 else "launches"),
+    }
+    if copy_gbs:
+        out["copy_ceiling_GBs"] = copy_gbs
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return out
+
+
+def one_step_line(r, copy_gbs):
+    ms = r.get("one_step_ms")
+    if not ms:
+        return None
+    bpl = r["bytes_per_launch"]
+    gbs = bpl / (ms * 1e-3) / 1e9
+    d = dict(kernel="lbm::tile_step_kernel", kernel_us=round(1e3 * ms, 3),
+             achieved_GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+             kernel_mlups=round(r["nodes"] / (ms * 1e-3) / 1e6, 1))
+    if copy_gbs:
+        d["frac_of_copy"] = round(gbs / copy_gbs, 4)
+    return d
+
+
+def traffic_of(key):
+    """HBM bytes per launch from the rocprofv3 counters recorded in profiles/,
+    valid only for the kernel source they were measured on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        tr = json.load(fh)
+    if tr.get("kernel_sha") == kernel_sha() and key in tr.get("per_launch", {}):
+        e = tr["per_launch"][key]
+        return e["bytes_per_launch"], e["ratio"]
+    return None
 
 
 def cpu_baseline(name, collision, budget_s=10.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (the same lattice advanced from the same start)."""
-    import numpy as np
-
     import oracle as O
-    from paper_2103_02119_amd import inputs as I
 
-    w = WORKLOADS[name]
-    nx, ny, r, cs2 = w["nx"], w["ny"], w["r"], w["cs2"]
-    nu = w["U"] * nx / w["Re"] if "Re" in w else w["nu"]
-    tau = nu / cs2 + 0.5
-    rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
-    uw = ((0, 0), (0, 0), (0, 0), (w["U"], 0)) if name == "cavity" else ((0, 0),) * 4
+    w, nx, ny, r, cs2, nu, tau, rates, uw = params_of(name)
     p = O.make_params(nx, ny, r, cs2, rates, bc=w["bc"], u_wall=uw, collision=collision)
-    if name == "cavity":
-        f = O.init(p, *I.cavity_rest(nx, ny))
-    elif name == "tgv":
-        f = O.init(p, *I.taylor_green(nx, ny, r, w["U"], cs2))
-    else:
-        f = O.init(p, *I.shear_layer(nx, ny, r, u0=w["U"]))
-    f = O.run(p, f, 1)  # first-touch / page-in
+    f = O.init(p, *initial_fields(name, nx, ny, r, w, cs2))
+    f = O.run(p, f, 1)  # first touch
     steps, t = 0, 0.0
-    chunk = 2
     while t < budget_s:
         t0 = time.perf_counter()
-        f = O.run(p, f, chunk)
+        f = O.run(p, f, 1)
         t += time.perf_counter() - t0
-        steps += chunk
+        steps += 1
     assert np.isfinite(f).all()
     cores = O.max_threads()
-    # the same oracle on one thread, for a quarter of the budget
     O.set_threads(1)
     steps1, t1 = 0, 0.0
     try:
@@ -171,20 +349,21 @@ def cpu_baseline(name, collision, budget_s=10.0):
                 kind="oracle",
                 sample=f"{name} {nx}x{ny} r={r}, FP64 oracle, {steps} steps ({t:.1f} s) "
                        f"from the same start, {'RC' if collision == 0 else 'RNR'}",
-                single_core_value=round(nx * ny * steps1 / t1 / 1e6, 3))
+                cpu_model=cpu_model(),
+                single_core_value=round(nx * ny * steps1 / t1 / 1e6, 3),
+                single_core_sample=f"{steps1} steps ({t1:.1f} s) on one thread")
 
 
-def time_to_steady(name, tol=1e-8, check_every=1000, cap=2_000_000):
-    """Cold start (fluid at rest) to a per-step residual <= tol, in FP64:
-    FP32 storage has a residual floor near 1e-7..1e-6 (rounding noise keeps
-    the weakly damped acoustic modes alive), so it never reaches 1e-8.
-    Returns steps and wall seconds (the residual is checked every
-    `check_every` steps, so steps are resolved to that)."""
+def time_to_steady(tol=1e-8, check_every=1000, cap=2_000_000):
+    """The 512 x 1024 cavity from rest to a per-step residual <= tol, in
+    FP64 (FP32 storage has a residual floor near 1e-7..1e-6: rounding noise
+    keeps the weakly damped acoustic modes alive, so it never reaches 1e-8).
+    Returns steps (resolved to `check_every`) and wall seconds."""
     import torch
 
     from paper_2103_02119_amd import lbm as L
 
-    lat, _ = setup(name, L.LBM_FP64, L.LBM_RC)
+    lat, _ = setup("cavity", L.LBM_FP64, L.LBM_RC)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps, R = 0, float("inf")
@@ -196,11 +375,10 @@ def time_to_steady(name, tol=1e-8, check_every=1000, cap=2_000_000):
             break
     wall = time.perf_counter() - t0
     lat.close()
-    return dict(cold_steps=steps if R <= tol else None, cold_seconds=round(wall, 3),
+    return dict(workload="cavity 512x1024 r=0.5 Re=1000 lid=0.05, from rest",
+                cold_steps=steps if R <= tol else None, cold_seconds=round(wall, 3),
                 residual=R, tol=tol, precision="fp64", collision="RC",
-                checked_every=check_every, warm_steps=None, warm_seconds=None,
-                warm_start="not on this lattice: the network is trained on 256x128 cavities "
-                           "with obstacles (python -m paper_2103_02119_amd.warmstart)")
+                checked_every=check_every)
 
 
 def bench_sweep(args):
@@ -236,7 +414,7 @@ def bench_sweep(args):
     kern_ms = e0.elapsed_time(e1) / steps
     achieved = bytes_per_lu * nodes / (kern_ms * 1e-3) / 1e9
     out = {
-        "metric": "MLUPS + % HBM roofline; time-to-steady-state warm-start vs cold",
+        "metric": METRIC,
         "value": round(nodes * steps / wall / 1e6, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -279,47 +457,52 @@ def bench_sweep(args):
     print(json.dumps(out), flush=True)
 
 
-def copy_probe(nbytes=1 << 30, reps=20):
-    """Plain device copy of a known size (counter calibration and the
-    achievable HBM bandwidth)."""
+def copy_probe_main(nbytes=1 << 30, reps=20):
+    """Plain device copies of a known size by the library's copy kernel
+    (counter calibration)."""
     import torch
 
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    from paper_2103_02119_amd import lbm as L
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
     b = torch.empty_like(a)
-    b.copy_(a)
+    s = torch.cuda.current_stream()
+    L.lbm_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, 0, s.cuda_stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(s)
     for _ in range(reps):
-        b.copy_(a)
-    e1.record()
+        L.lbm_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, 0, s.cuda_stream)
+    e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     print(json.dumps({"copy_bytes": nbytes, "read_plus_write_GBs": round(2 * nbytes / ms / 1e6, 1),
-                      "ms": round(ms, 4)}), flush=True)
+                      "ms": round(ms, 4), "dispatches": reps + 1}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["sweep"], default="cavity")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["sweep"], default="shear")
+    ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
+    ap.add_argument("--steps-per-launch", type=int, choices=[0, 1, 2], default=0,
+                    help="0 = the library's automatic choice")
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--chunk", type=int, default=100, help="steps per host call")
     ap.add_argument("--graph-steps", type=int, default=64, help="sweep: steps per captured graph")
     ap.add_argument("--steady-cap", type=int, default=0,
                     help="sweep: also run every case to --steady-tol, at most this many steps")
     ap.add_argument("--steady-tol", type=float, default=1e-6)
     ap.add_argument("--steady-every", type=int, default=1000)
-    ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
-    ap.add_argument("--check-every", type=int, default=100)
-    ap.add_argument("--chunk", type=int, default=100, help="launches per host call")
-    ap.add_argument("--rows", type=int, default=0, help="rows per wavefront (0 = automatic)")
-    ap.add_argument("--no-rnr", action="store_true", help="skip the RNR side-by-side timing")
+    ap.add_argument("--minimal", action="store_true",
+                    help="only the headline workload (no copy ceiling, FP64, RNR, cavity, "
+                         "time to steady state or CPU baseline); for profiling runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-steady", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--no-steady", action="store_true",
-                    help="skip the cold-start time-to-steady-state run (cavity only)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -334,101 +517,89 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe:
-        copy_probe()
+        copy_probe_main()
         return
     if args.workload == "sweep":
         bench_sweep(args)
         return
-    prec = L.LBM_FP32_DEV if args.precision == "fp32dev" else L.LBM_FP64
-    bytes_per_lu = 72 if prec == L.LBM_FP32_DEV else 144
-
-    lat, info = setup(args.workload, prec, L.LBM_RC, args.rows)
-    nodes = info["nx"] * info["ny"]
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-    wall, kern, blew_up = time_steps(lat, args.steps, args.check_every, args.chunk)
-    try:
-        R = lat.residual()
-        sums = lat.sums()
-    except L.LbmError as e:
-        if e.code != L.LBM_E_UNSTABLE:
-            raise
-        R, sums = float("nan"), [float("nan")] * 3
-        blew_up = blew_up or args.warmup + args.steps
-    rows, wgs = lat.launch_shape()
-    lat.close()
-
-    rnr = None
-    if not args.no_rnr:
-        lat2, _ = setup(args.workload, prec, L.LBM_RNR, args.rows)
-        lat2.step(args.warmup)
-        wall2, kern2, _ = time_steps(lat2, args.steps, args.check_every, args.chunk)
-        lat2.close()
-        rnr = dict(mlups=round(nodes * args.steps / wall2 / 1e6, 1),
-                   kernel_us=round(1e3 * sum(kern2) / len(kern2), 3))
-
-    mlups = nodes * args.steps / wall / 1e6
-    kern_ms = sum(kern) / len(kern)
-    achieved = bytes_per_lu * nodes / (kern_ms * 1e-3) / 1e9
-    # HBM bytes per launch from the rocprofv3 counters recorded in profiles/,
-    # valid only for the kernel source they were measured on
-    traffic, traffic_ratio = None, None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        key = f"{args.workload}/{args.precision}"
-        if tr.get("kernel_sha") == kernel_sha() and key in tr.get("per_launch", {}):
-            traffic = tr["per_launch"][key]["bytes_per_launch"]
-            traffic_ratio = tr["per_launch"][key]["ratio"]
-
+    print(f"bench: workload {args.workload} {args.precision}, {args.steps} steps", file=sys.stderr,
+          flush=True)
+    full = not args.minimal
+    vb = 4 if args.precision == "fp32dev" else 8
+    w = WORKLOADS[args.workload]
+    buf_bytes = L.lbm_required_bytes(w["nx"], w["ny"], L.LBM_FP32_DEV if vb == 4 else L.LBM_FP64)
+    # one population buffer copied: the same bytes each way as one step moves
+    copy = copy_ceiling(buf_bytes) if full else None
+    copy_gbs = copy["GBs"] if copy else None
+    main_r = run_workload(args.workload, args.precision, L.LBM_RC, args, args.steps_per_launch,
+                          one_step=full)
+    info = main_r["info"]
+    tr = traffic_of(f"{args.workload}/{args.precision}/{main_r['steps_per_launch']}")
     out = {
-        "metric": "MLUPS + % HBM roofline; time-to-steady-state warm-start vs cold",
-        "value": round(mlups, 1),
+        "metric": METRIC,
+        "value": round(main_r["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 5),
+        "ms_per_step": round(1e3 * main_r["wall"] / args.steps, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == L.LBM_FP32_DEV else "f64",
+        "dtype": "f32" if vb == 4 else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload} {info['nx']}x{info['ny']} r={info['r']}"
-                        + (f" Re={WORKLOADS[args.workload]['Re']:g} lid={WORKLOADS[args.workload]['U']}"
-                           if args.workload == "cavity" else ""),
-            "collision": "RC (RNR beside it)",
-            "storage": "FP32 deviations f - w rho0" if prec == L.LBM_FP32_DEV else "FP64",
-            "cs2": info["cs2"], "tau": round(info["tau"], 6),
-            "residual_every": args.check_every,
-            "residual_read": "asynchronous, one interval later",
-            "launches_per_host_call": args.chunk,
-            "rows_per_wave": rows, "workgroups": wgs,
+                        + (f" Re={w['Re']:g} lid={w['U']}" if args.workload == "cavity" else "")
+                        + (" kappa=80 delta=0.05 u0=0.04 doubly periodic" if args.workload == "shear"
+                           else ""),
+            "collision": "RC",
+            "storage": "FP32 deviations f - w rho0" if vb == 4 else "FP64",
+            "cs2": info["cs2"], "nu": info["nu"], "tau": round(info["tau"], 6),
+            "population_buffers_bytes": 2 * buf_bytes,
+            "steps_per_launch": main_r["steps_per_launch"],
+            "checks_in_timed_region": main_r["checks"],
+            "check_every": args.check_every,
+            "check_read": "asynchronous, one interval later; the last before the clock stops",
+            "steps_per_host_call": args.chunk,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "traffic_over_algorithmic": traffic_ratio,
-            "algorithmic_bytes_per_launch": bytes_per_lu * nodes,
-            "kernel": "lbm::tile_step_kernel" if args.rows == 0 else "lbm::step_kernel",
-            "bytes_per_lu": bytes_per_lu,
-            "kernel_us": round(1e3 * kern_ms, 3),
-        },
-        "rnr": rnr,
-        "final_residual": R,
-        "mass": sums[0],
-        "nonfinite_at_step": blew_up,
+        "roofline": roofline_of(main_r, copy_gbs, tr),
+        "target_mlups": round(TARGET_MLUPS[args.precision], 1),
+        "mlups_vs_target": round(main_r["mlups"] / TARGET_MLUPS[args.precision], 4),
+        "one_step_per_launch": one_step_line(main_r, copy_gbs),
+        "final_residual": main_r["residual"],
+        "mass": main_r["mass"],
+        "nonfinite_at_step": main_r["nonfinite_at_step"],
+        "copy_ceiling": copy,
     }
-    if args.workload == "cavity" and not args.no_steady:
-        out["time_to_steady"] = time_to_steady(args.workload)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, L.LBM_RC, args.cpu_budget)
+    if full:
+        if args.precision == "fp32dev":
+            r64 = run_workload(args.workload, "fp64", L.LBM_RC, args)
+            c64 = copy_gbs  # the copy ceiling does not depend on the value type
+            out["fp64"] = dict(mlups=round(r64["mlups"], 1),
+                               roofline=roofline_of(r64, c64),
+                               one_step_per_launch=one_step_line(r64, c64),
+                               target_mlups=round(TARGET_MLUPS["fp64"], 1),
+                               mlups_vs_target=round(r64["mlups"] / TARGET_MLUPS["fp64"], 4))
+        rn = run_workload(args.workload, args.precision, L.LBM_RNR, args, args.steps_per_launch,
+                          one_step=False)
+        out["rnr"] = dict(mlups=round(rn["mlups"], 1), kernel_us=round(1e3 * rn["kernel_ms"], 3),
+                          steps_per_launch=rn["steps_per_launch"])
+        if args.workload != "cavity":
+            cav = run_workload("cavity", args.precision, L.LBM_RC, args)
+            d = dict(workload="cavity 512x1024 r=0.5 Re=1000 lid=0.05 (both buffers fit the "
+                              "256 MB Infinity Cache: not an HBM roofline)",
+                     mlups=round(cav["mlups"], 1), steps_per_launch=cav["steps_per_launch"],
+                     kernel_us=round(1e3 * cav["kernel_ms"], 3),
+                     one_step_kernel_us=round(1e3 * cav["one_step_ms"], 3))
+            if "two_step_ms" in cav:
+                d["two_step_kernel_us"] = round(1e3 * cav["two_step_ms"], 3)
+            out["cavity_cache_resident"] = d
+        if not args.no_steady:
+            out["time_to_steady"] = time_to_steady()
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(args.workload, L.LBM_RC, args.cpu_budget)
+    out["kernel_sha"] = kernel_sha()
     print(json.dumps(out), flush=True)
 
 
