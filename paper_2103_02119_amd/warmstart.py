@@ -439,15 +439,21 @@ def build_dataset(params, nx=256, ny=128, U=0.05, precision=L.LBM_FP32_DEV, tol=
 
 
 def train(net, X, T, F, epochs, lr_max=1e-3, lr_min=2e-5, val=None, channel_weights=(0.25, 1, 1),
-          log=_log_default):
+          seconds=None, log=_log_default):
     """Adam with a cosine learning-rate schedule; returns the loss history.
     The pressure channel is weighted down: an initial density error costs
-    the lattice run little, a velocity error much more."""
+    the lattice run little, a velocity error much more.  With `seconds` the
+    epoch count is cut to what fits that time, judged from the first epoch."""
     tr = Trainer(net, X, T, F)
     tr.cw.copy_(net.torch.tensor(channel_weights, dtype=net.torch.float32))
     hist = []
     t0 = time.perf_counter()
-    for e in range(epochs):
+    e = 0
+    while e < epochs:
+        if seconds and e == 1:
+            per = time.perf_counter() - t0
+            epochs = max(2, min(epochs, int(seconds / per)))
+            log(f"train: {per:.1f} s per epoch, {epochs} epochs fit {seconds:.0f} s")
         lr = lr_min + 0.5 * (lr_max - lr_min) * (1 + np.cos(np.pi * e / max(epochs - 1, 1)))
         loss = tr.epoch(lr)
         rec = dict(epoch=e, lr=float(lr), loss=loss)
@@ -457,6 +463,7 @@ def train(net, X, T, F, epochs, lr_max=1e-3, lr_min=2e-5, val=None, channel_weig
         if e % 10 == 9 or e == epochs - 1:
             log(f"train: epoch {e + 1}/{epochs} loss {loss:.4g}"
                 + (f" val {rec['val']:.4g}" if "val" in rec else "") + f" {time.perf_counter() - t0:.1f} s")
+        e += 1
     return hist, time.perf_counter() - t0
 
 
@@ -478,8 +485,23 @@ def predict_fields(net, scales, masks, params):
 SETTLE_STEPS = 50   # steps before the smoothing step of a start from fields
 
 
+MODES = ("cold", "cold+smooth", "warm", "warm+smooth")
+
+
+def _compare(res, ref, mode):
+    """Steps of `mode` against `ref` over the cases both reached."""
+    both = (res[ref]["steps"] > 0) & (res[mode]["steps"] > 0)
+    sc, sw = res[ref]["steps"][both], res[mode]["steps"][both]
+    return dict(compared=int(both.sum()), steps_total=int(sw.sum()),
+                ref_steps_total=int(sc.sum()),
+                step_speedup_total=float(sc.sum() / max(sw.sum(), 1)),
+                step_speedup_median=float(np.median(sc / sw)) if len(sc) else None,
+                step_speedup_range=[float((sc / sw).min()), float((sc / sw).max())]
+                if len(sc) else None)
+
+
 def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_every=1000,
-                 max_steps=400_000, log=_log_default):
+                 max_steps=400_000, modes=None, log=_log_default):
     """Steps and wall time to a per-step residual of tol (FP64; the plain
     lattice Boltzmann scheme decides convergence) for the same cases started
       cold        from rest,
@@ -496,7 +518,7 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
 
     masks = [I.cavity_obstacles(nx, ny, p["mask_seed"]) for p in params]
     res = {}
-    for mode in ("cold", "cold+smooth", "warm", "warm+smooth"):
+    for mode in (modes or MODES):
         b = L.Batch(cavity_cases(params, nx, ny, U), precision=L.LBM_FP64)
         for c, m in enumerate(masks):
             b.set_mask(c, m)
@@ -517,40 +539,123 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
         b.close()
         res[mode] = dict(steps=steps, seconds=wall, inference_seconds=t_inf)
         log(f"{mode}: {int((steps > 0).sum())}/{len(params)} reached {tol:g} in {wall:.1f} s")
-    out = dict(tol=tol, cases=len(params), settle_steps=SETTLE_STEPS,
-               inference_seconds=round(res["warm+smooth"]["inference_seconds"], 3))
+    out = dict(tol=tol, cases=len(params), settle_steps=SETTLE_STEPS, check_every=check_every,
+               max_steps=max_steps)
     for mode, r in res.items():
         out[mode] = dict(reached=int((r["steps"] > 0).sum()), seconds=round(r["seconds"], 3))
-    ref = "cold"
-    for mode in ("cold+smooth", "warm", "warm+smooth"):
-        both = (res[ref]["steps"] > 0) & (res[mode]["steps"] > 0)
-        sc, sw = res[ref]["steps"][both], res[mode]["steps"][both]
-        out[mode].update(compared=int(both.sum()), steps_total=int(sw.sum()),
-                         cold_steps_total=int(sc.sum()),
-                         step_speedup_total=float(sc.sum() / max(sw.sum(), 1)),
-                         step_speedup_median=float(np.median(sc / sw)) if len(sc) else None)
-    out["wall_speedup_warm_smooth_vs_cold"] = float(res["cold"]["seconds"] / res["warm+smooth"]["seconds"])
+        if mode.startswith("warm"):
+            out["inference_seconds"] = round(r["inference_seconds"], 3)
+    # against the plain scheme from rest
+    if "cold" in res:
+        for mode in res:
+            if mode != "cold":
+                out[mode]["vs_cold"] = _compare(res, "cold", mode)
+    # the network's own gain: the same start-up treatment with and without it
+    for warm, cold in (("warm+smooth", "cold+smooth"), ("warm", "cold")):
+        if warm in res and cold in res:
+            c = _compare(res, cold, warm)
+            c["wall_speedup"] = float(res[cold]["seconds"] / res[warm]["seconds"])
+            out[f"network_gain_{warm}_vs_{cold}"] = c
     out["per_case"] = [dict(Re=round(p["Re"], 1), r=p["r"],
                             **{m: int(res[m]["steps"][c]) for m in res}) for c, p in enumerate(params)]
     return out
 
 
+def build_dataset_budget(target, gen_batch, seconds, seed, re_range, nx, ny, precision, tol,
+                         max_steps, log=_log_default):
+    """build_dataset over successive batches of gen_batch seeded cases until
+    `target` fields have converged or `seconds` have passed (checked between
+    batches); the cases are the first ones of one seeded sequence, so a
+    larger budget extends a smaller one's dataset."""
+    from . import inputs as I
+
+    t0 = time.perf_counter()
+    parts, infos = [], []
+    allp = I.warmstart_cases(gen_batch * 64, seed=seed, re_range=re_range)
+    k = 0
+    while True:
+        params = allp[k * gen_batch:(k + 1) * gen_batch]
+        parts.append(build_dataset(params, nx=nx, ny=ny, precision=precision, tol=tol,
+                                   max_steps=max_steps, log=log))
+        infos.append(parts[-1][4])
+        k += 1
+        got = sum(p[0].shape[0] for p in parts)
+        log(f"dataset: {got} fields from {k * gen_batch} cases, {time.perf_counter() - t0:.0f} s")
+        if got >= target or time.perf_counter() - t0 > seconds or k * gen_batch >= len(allp):
+            break
+    X = np.concatenate([p[0] for p in parts])
+    fields = tuple(np.concatenate([p[1][i] for p in parts]) for i in range(3))
+    masks = [m for p in parts for m in p[2]]
+    kept = [q for p in parts for q in p[3]]
+    keys = ("cases", "converged", "blew_up", "not_converged")
+    info = {key: int(sum(i[key] for i in infos)) for key in keys}
+    info.update(seconds=round(time.perf_counter() - t0, 2), tol=tol, batches=k,
+                median_steps=int(np.median([i["median_steps"] for i in infos if i["median_steps"]]))
+                if any(i["median_steps"] for i in infos) else None)
+    return X, fields, masks, kept, info
+
+
+def save_weights(net, scales, path):
+    """The trained network's parameters: 3x3 and head weights rounded to BF16
+    (the precision the forward pass uses them in) and stored as their raw
+    16-bit patterns, biases in FP32.  numpy .npz, no pickled objects."""
+    import torch
+
+    out = {"U": np.float64(scales.U), "levels": np.asarray(net.levels, np.int32)}
+    for k, v in net.state().items():
+        if k.endswith(".W"):
+            bf = torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(torch.bfloat16)
+            out[k] = bf.view(torch.int16).numpy().view(np.uint16)
+        else:
+            out[k] = np.asarray(v, np.float32)
+    np.savez_compressed(path, **out)
+
+
+def load_weights(path, batch=16, H=128, W=256):
+    """A WarmStartNet (device buffers for `batch` inputs of H x W) and its
+    output scales from save_weights' file."""
+    import torch
+
+    with np.load(path, allow_pickle=False) as z:
+        levels = tuple(int(c) for c in z["levels"])
+        net = WarmStartNet(H=H, W=W, batch=batch, levels=levels)
+        st = {}
+        for k in z.files:
+            if k in ("U", "levels"):
+                continue
+            v = z[k]
+            if v.dtype == np.uint16:
+                v = torch.from_numpy(v.view(np.int16)).view(torch.bfloat16).float().numpy()
+            st[k] = v
+        net.load_state(st)
+        return net, Scales(float(z["U"]))
+
+
 def run_pipeline(n_train=3200, n_test=64, epochs=120, batch=16, seed=2103, test_seed=77,
                  out_dir=None, nx=256, ny=128, gen_max_steps=150_000, eval_max_steps=400_000,
                  re_range=(100.0, 5000.0), gen_precision=L.LBM_FP32_DEV, gen_tol=2e-6,
+                 target_fields=None, gen_seconds=None, gen_batch=1600, train_seconds=None,
                  log=_log_default):
     """Generate steady fields with the batched solver, train the network on
-    them, then compare cold and warm starts on unseen cases."""
+    them, then compare cold and warm starts on unseen cases.  With
+    target_fields the generation runs in batches of gen_batch cases until
+    that many fields have converged or gen_seconds have passed."""
     import json
     import os
 
     from . import inputs as I
 
     t0 = time.perf_counter()
-    params = I.warmstart_cases(n_train, seed=seed, re_range=re_range)
-    X, (rho, ux, uy), masks, kept, gen_info = build_dataset(params, nx=nx, ny=ny,
-                                                            precision=gen_precision, tol=gen_tol,
-                                                            max_steps=gen_max_steps, log=log)
+    if target_fields:
+        X, (rho, ux, uy), masks, kept, gen_info = build_dataset_budget(
+            target_fields, gen_batch, gen_seconds or 1e9, seed, re_range, nx, ny, gen_precision,
+            gen_tol, gen_max_steps, log=log)
+    else:
+        params = I.warmstart_cases(n_train, seed=seed, re_range=re_range)
+        X, (rho, ux, uy), masks, kept, gen_info = build_dataset(params, nx=nx, ny=ny,
+                                                                precision=gen_precision,
+                                                                tol=gen_tol,
+                                                                max_steps=gen_max_steps, log=log)
     log(f"dataset: {gen_info}")
     from . import workloads as Wk
 
@@ -560,25 +665,41 @@ def run_pipeline(n_train=3200, n_test=64, epochs=120, batch=16, seed=2103, test_
     nval = max(batch, len(X) // 10)
     net = WarmStartNet(H=X.shape[1], W=X.shape[2], batch=batch, seed=seed)
     hist, t_train = train(net, X[nval:], T[nval:], fluid[nval:], epochs,
-                          val=(X[:nval], T[:nval], fluid[:nval]), log=log)
+                          val=(X[:nval], T[:nval], fluid[:nval]), seconds=train_seconds, log=log)
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        save_weights(net, scales, os.path.join(out_dir, "warmstart_weights.npz"))
+        log(f"weights saved to {out_dir}")
     test = I.warmstart_cases(n_test, seed=test_seed, re_range=re_range)
-    cmp = warm_vs_cold(net, scales, test, nx=nx, ny=ny, max_steps=eval_max_steps, log=log)
+    cmp = (warm_vs_cold(net, scales, test, nx=nx, ny=ny, max_steps=eval_max_steps, log=log)
+           if n_test else None)
     # the validation error of predicting the rest state (all zeros), over the
     # same whole batches that the validation loss covers
     nv = (nval // batch) * batch
     val_zero = float((T[:nv] ** 2 * fluid[:nv, ..., None]).sum() / max(int(fluid[:nv].sum()), 1))
     metrics = dict(dataset=gen_info, train_samples=int(len(X) - nval),
-                   val_samples=int(nval), epochs=epochs, batch=batch,
+                   val_samples=int(nval), epochs=len(hist), batch=batch,
                    train_seconds=round(t_train, 2), final_loss=hist[-1]["loss"],
                    final_val=hist[-1].get("val"), val_zero_prediction=val_zero, warm_vs_cold=cmp,
                    total_seconds=round(time.perf_counter() - t0, 1))
     if out_dir:
-        os.makedirs(out_dir, exist_ok=True)
-        np.savez_compressed(os.path.join(out_dir, "warmstart_weights.npz"), U=scales.U,
-                            **{k: v.astype(np.float32) for k, v in net.state().items()})
         with open(os.path.join(out_dir, "warmstart_metrics.json"), "w") as fh:
             json.dump(dict(metrics, history=hist), fh, indent=1)
     return metrics, net, scales
+
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__),
+                                     "warmstart_cavity_256x128.npz")
+
+
+def evaluate(weights=WEIGHTS, n_test=64, test_seed=77, max_steps=400_000, modes=None,
+             log=_log_default):
+    """warm_vs_cold for n_test unseen seeded cases with saved weights."""
+    from . import inputs as I
+
+    net, scales = load_weights(weights)
+    test = I.warmstart_cases(n_test, seed=test_seed)
+    return warm_vs_cold(net, scales, test, max_steps=max_steps, modes=modes, log=log)
 
 
 if __name__ == "__main__":
@@ -587,11 +708,34 @@ if __name__ == "__main__":
 
     ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
     ap.add_argument("--train-cases", type=int, default=3200)
+    ap.add_argument("--target-fields", type=int, default=0,
+                    help="generate batches of cases until this many fields converged")
+    ap.add_argument("--gen-seconds", type=float, default=0.0,
+                    help="stop generating new batches after this many seconds")
+    ap.add_argument("--gen-max-steps", type=int, default=150_000)
     ap.add_argument("--test-cases", type=int, default=64)
     ap.add_argument("--epochs", type=int, default=120)
+    ap.add_argument("--train-seconds", type=float, default=0.0,
+                    help="cut the epoch count to what fits this time")
+    ap.add_argument("--gen-batch", type=int, default=1600)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
+                    help="skip training: evaluate saved weights on --test-cases unseen cases")
     a = ap.parse_args()
-    m, _, _ = run_pipeline(a.train_cases, a.test_cases, a.epochs, out_dir=a.out)
-    m = dict(m)
-    m["warm_vs_cold"] = {k: v for k, v in m["warm_vs_cold"].items() if k != "per_case"}
-    print(json.dumps(m), flush=True)
+    if a.eval_only:
+        cmp = evaluate(a.eval_only, a.test_cases)
+        if a.out:
+            import os
+            os.makedirs(a.out, exist_ok=True)
+            with open(os.path.join(a.out, "warmstart_eval.json"), "w") as fh:
+                json.dump(cmp, fh, indent=1)
+        print(json.dumps({k: v for k, v in cmp.items() if k != "per_case"}), flush=True)
+    else:
+        m, _, _ = run_pipeline(a.train_cases, a.test_cases, a.epochs, out_dir=a.out,
+                               target_fields=a.target_fields or None,
+                               gen_seconds=a.gen_seconds or None, gen_max_steps=a.gen_max_steps,
+                               gen_batch=a.gen_batch, train_seconds=a.train_seconds or None)
+        m = dict(m)
+        if m["warm_vs_cold"]:
+            m["warm_vs_cold"] = {k: v for k, v in m["warm_vs_cold"].items() if k != "per_case"}
+        print(json.dumps(m), flush=True)
