@@ -140,7 +140,7 @@ int lbm_step(lbm_ctx *ctx, long n);
  * population buffers exceed the GPU's 256 MB Infinity Cache, one below.  With
  * an explicit 2 an lbm_step call advances pairs of steps while two remain, so
  * after an even count the state one step back is not held and lbm_residual /
- * lbm_check_async return LBM_E_STATE until a one-step launch
+ * lbm_check_async / lbm_check_into return LBM_E_STATE until a one-step launch
  * (an odd count, or lbm_step(ctx, 1)).
  * Errors: LBM_E_INVAL (ctx NULL, k not 0, 1 or 2). */
 int lbm_set_steps_per_launch(lbm_ctx *ctx, int k);
@@ -198,6 +198,25 @@ int lbm_sums(lbm_ctx *ctx, double out[3]);
  * (*R is then NaN; *step names the check); LBM_E_DEVICE. */
 int lbm_check_async(lbm_ctx *ctx);
 int lbm_check_result(lbm_ctx *ctx, double *R, double sums[3], long *step);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_check_async's fused
+ * residual-and-sums pass with its per-workgroup partial sums in a static
+ * device array of the library (at most 4096 workgroups x 8 FP64 values,
+ * 256 KiB, one per GPU, held until the process ends) and its results written
+ * to out, caller-owned device memory of 8 doubles:
+ *   out[0] = sum |u^n - u^{n-1}|^2, out[1] = sum |u^n|^2 (R = sqrt(out[0]) /
+ *   sqrt(out[1])), out[2] = 0, out[3] != 0 if a velocity was NaN or Inf;
+ *   out[4..6] = sum rho, sum rho ux, sum rho uy (as lbm_sums),
+ *   out[7] != 0 if a density or velocity was NaN or Inf.
+ * Enqueues on the context's stream and returns without waiting; calls no
+ * allocating routine.  Every call on one GPU shares its array: calls that
+ * overlap on one GPU (other streams, other host threads) race, so order them
+ * on one stream.  The reduction size is bounded by construction; a lattice
+ * needing more partials than the array holds is rejected with LBM_E_INVAL.
+ * Errors: LBM_E_INVAL (NULL argument), LBM_E_STATE (as lbm_residual),
+ * LBM_E_DEVICE. */
+int lbm_check_into(lbm_ctx *ctx, double *out);
 
 /* Copies the populations f_i(x, t) of the current time level (after
  * streaming, before collision) to / from host double[9][ny][nx].

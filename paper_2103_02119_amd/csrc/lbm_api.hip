@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/lbm.h"
@@ -27,6 +28,30 @@ enum Form { kEmpty = 0, kPre = 1, kPost = 2 };
 // reduction partials (up to 8 values per block), then the results
 static constexpr size_t kResults = 8 * static_cast<size_t>(kMaxPartials);
 
+// Scratch of the allocation-free check (lbm_check_into): the per-workgroup
+// partial sums of the fused residual-and-sums reduction, at most kMaxPartials
+// workgroups of 8 values (256 KiB).  Each GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address on each GPU is looked up
+// once (scratch_on) and only that address is handed to kernels.
+static constexpr size_t kScratchDoubles = 8 * static_cast<size_t>(kMaxPartials);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on device dev (which must be current);
+// nullptr if it cannot be found.
+static double *scratch_on(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
 
 struct lbm_ctx {
     int nx, ny;
@@ -56,6 +81,7 @@ struct lbm_ctx {
     unsigned char *d_mask;        // obstacle mask [ny][pitch] (or null)
     unsigned char *d_tile_solid;  // per step tile: obstacle in its neighbourhood
     int steps_per_launch;         // 0 automatic, 1, 2 (lbm_set_steps_per_launch)
+    double *scratch;              // device address of `scratch` on this context's GPU
     long steps;
     char err[512];
 };
@@ -395,6 +421,14 @@ extern "C" int lbm_create(int nx, int ny, double r, const double rates[9], const
         }
     }
     if (status == LBM_OK) {
+        // the allocation-free check's scratch on this GPU, looked up once per
+        // device while it is current
+        int dev = -1;
+        if (hipGetDevice(&dev) == hipSuccess) c->scratch = scratch_on(dev);
+        if (!c->scratch)
+            status = fail_ctx(nullptr, LBM_E_DEVICE, "device address of the check scratch not found");
+    }
+    if (status == LBM_OK) {
         c->cur = 0;
         status = init_fields_device(c, nullptr, nullptr, nullptr);
         if (status != LBM_OK) snprintf(g_create_error, sizeof(g_create_error), "%s", c->err);
@@ -600,6 +634,27 @@ extern "C" int lbm_check_async(lbm_ctx *c) {
                                   c->stream));
     HIP_OR_FAIL(c, hipEventRecord(c->check_ev, c->stream));
     c->check_step = c->steps;
+    return LBM_OK;
+}
+
+// lbm_check_async's reductions with the partial sums in the static scratch
+// of this GPU and the eight results written to the caller's device memory:
+// no allocation of any kind, no host wait.  Every partial the finalize pass
+// reads is written by the same call, so nothing in the scratch needs
+// clearing first.
+extern "C" int lbm_check_into(lbm_ctx *c, double *out) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (!out) return fail_ctx(c, LBM_E_INVAL, "out is NULL");
+    if (!c->prev_valid || c->form[1 - c->cur] == kEmpty)
+        return fail_ctx(c, LBM_E_STATE, "the state one step before the current one is not held");
+    const size_t need = 8 * static_cast<size_t>(reduce_partials(c->G));
+    if (need > kScratchDoubles)
+        return fail_ctx(c, LBM_E_INVAL, "the check needs %zu scratch values, the maximum is %zu",
+                        need, kScratchDoubles);
+    const int p = 1 - c->cur;
+    HIP_OR_FAIL(c, launch_check(c->prec, c->form[c->cur] == kPost, c->f[c->cur],
+                                c->form[p] == kPost, c->f[p], c->scratch, out, c->G, c->Kd,
+                                c->Kf, c->H, c->stream));
     return LBM_OK;
 }
 

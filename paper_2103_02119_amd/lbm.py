@@ -28,7 +28,7 @@ LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
            "lbm_set_steps_per_launch", "lbm_steps_per_launch",
            "lbm_moments", "lbm_stress", "lbm_residual", "lbm_sums", "lbm_check_async",
-           "lbm_check_result", "lbm_get_populations", "lbm_set_populations",
+           "lbm_check_result", "lbm_check_into", "lbm_get_populations", "lbm_set_populations",
            "lbm_set_mask", "lbm_set_rates", "lbm_set_force", "lbm_step_forced", "lbm_smooth_step",
            "lbm_stream_copy", "lbm_steps_done", "lbm_launch_shape", "lbm_last_error",
            "lbm_destroy")
@@ -127,6 +127,8 @@ def load():
     L.lbm_set_steps_per_launch.restype = ctypes.c_int
     L.lbm_steps_per_launch.argtypes = [_CTX]
     L.lbm_steps_per_launch.restype = ctypes.c_int
+    L.lbm_check_into.argtypes = [_CTX, ctypes.c_void_p]
+    L.lbm_check_into.restype = ctypes.c_int
     L.lbm_stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
                                   ctypes.c_void_p]
     L.lbm_stream_copy.restype = ctypes.c_int
@@ -307,6 +309,12 @@ def lbm_check_result(ctx):
     return R.value, out, step.value
 
 
+def lbm_check_into(ctx, out_ptr: int):
+    """Enqueue the fused check with its results written to device memory at
+    out_ptr (8 doubles, e.g. a torch float64 tensor's data_ptr())."""
+    _check(load().lbm_check_into(ctx, ctypes.c_void_p(int(out_ptr))), ctx)
+
+
 def lbm_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, workgroups: int = 0, stream=None):
     """The library's streaming copy kernel between two device buffers."""
     _check(load().lbm_stream_copy(ctypes.c_void_p(int(dst_ptr)), ctypes.c_void_p(int(src_ptr)),
@@ -423,6 +431,9 @@ class Lattice:
 
     def steps_per_launch(self):
         return lbm_steps_per_launch(self.ctx)
+
+    def check_into(self, out_ptr):
+        lbm_check_into(self.ctx, out_ptr)
 
     def moments(self):
         return lbm_moments(self.ctx, self.nx, self.ny)

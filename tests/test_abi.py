@@ -212,6 +212,7 @@ def test_null_handles_are_rejected_before_touching_the_device():
         "lbm_step_forced": (None, 1, pd, pd),
         "lbm_smooth_step": (None,),
         "lbm_set_steps_per_launch": (None, 1),
+        "lbm_check_into": (None, None),
     }
     for name, args in calls.items():
         assert getattr(lib, name)(*args) == L.LBM_E_INVAL, name
