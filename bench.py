@@ -239,6 +239,7 @@ def run_workload(name, prec_name, collision, args, spl=0, one_step=True):
     nodes = info["nx"] * info["ny"]
     k = spl or lat.steps_per_launch()
     lat.set_steps_per_launch(k)
+    form = lat.two_step_form()
     lat.step(args.warmup)
     torch.cuda.synchronize()
     wall, kern_ms, checks, blew_up = time_steps(lat, args.steps, args.check_every, args.chunk, k)
@@ -251,7 +252,9 @@ def run_workload(name, prec_name, collision, args, spl=0, one_step=True):
         R, sums = float("nan"), [float("nan")] * 3
         blew_up = blew_up or args.warmup + args.steps
     vb = 4 if prec == L.LBM_FP32_DEV else 8
-    out = dict(nodes=nodes, info=info, wall=wall, steps_per_launch=k, kernel_ms=kern_ms,
+    kernel = ("lbm::tile_step_kernel" if k == 1 else
+              "lbm::tile2_staged_kernel" if form == L.LBM_FORM_STAGED else "lbm::tile2_step_kernel")
+    out = dict(nodes=nodes, info=info, wall=wall, steps_per_launch=k, kernel_ms=kern_ms, kernel=kernel,
                mlups=nodes * args.steps / wall / 1e6, checks=checks, residual=R, mass=sums[0],
                nonfinite_at_step=blew_up, value_bytes=vb,
                bytes_per_launch=18 * vb * nodes)
@@ -277,7 +280,7 @@ def roofline_of(r, copy_gbs, traffic=None):
         "traffic": traffic[0] if traffic else None,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "traffic_over_algorithmic": traffic[1] if traffic else None,
-        "kernel": "lbm::tile2_step_kernel" if k == 2 else "lbm::tile_step_kernel",
+        "kernel": r["kernel"],
         "steps_per_launch": k,
         "algorithmic_bytes_per_launch": bpl,
         "bytes_per_lu": bpl // (k * r["nodes"]),

@@ -136,8 +136,8 @@ int lbm_step(lbm_ctx *ctx, long n);
  * step t-1 once, keep each tile's step-t state in on-chip memory and write
  * step t+1, halving the population traffic per step; results are bit-identical
  * to one step per launch.  They apply only without an obstacle mask (with a
- * mask every launch advances one step).  Automatic: two once the two
- * population buffers exceed the GPU's 256 MB Infinity Cache, one below.  With
+ * mask every launch advances one step).  Automatic: two on every lattice
+ * without a mask (measured faster from 64 x 32 nodes up).  With
  * an explicit 2 an lbm_step call advances pairs of steps while two remain, so
  * after an even count the state one step back is not held and lbm_residual /
  * lbm_check_async / lbm_check_into return LBM_E_STATE until a one-step launch
@@ -148,6 +148,25 @@ int lbm_set_steps_per_launch(lbm_ctx *ctx, int k);
 /* Steps per launch that lbm_step currently takes for a long run (1 or 2),
  * after the automatic choice and the mask rule; LBM_E_INVAL for a NULL ctx. */
 int lbm_steps_per_launch(const lbm_ctx *ctx);
+
+/* Form of the two-steps-per-launch kernel, a tuning choice with no effect on
+ * the results (both are bit-identical to one step per launch):
+ *   LBM_FORM_REGISTER  64 x 8 node tiles, the step-t values of a thread's
+ *                      nodes held in registers between phases;
+ *   LBM_FORM_STAGED    64 x 24 node tiles with every step-t value staged in
+ *                      on-chip memory, which recomputes fewer halo nodes
+ *                      (1.12 collisions per lattice update against 1.30);
+ *                      LBM_FP32_DEV only;
+ *   LBM_FORM_AUTO      (the default) staged for LBM_FP32_DEV once it has at
+ *                      least 1024 tiles, else register.
+ * Errors: LBM_E_INVAL (ctx NULL, an unknown form, LBM_FORM_STAGED with a
+ * precision other than LBM_FP32_DEV). */
+enum { LBM_FORM_AUTO = 0, LBM_FORM_REGISTER = 1, LBM_FORM_STAGED = 2 };
+int lbm_set_two_step_form(lbm_ctx *ctx, int form);
+
+/* The form the next two-step launch takes (LBM_FORM_REGISTER or
+ * LBM_FORM_STAGED), after the automatic choice; LBM_E_INVAL for a NULL ctx. */
+int lbm_two_step_form(const lbm_ctx *ctx);
 
 /* Macroscopic fields at the current time level: rho = sum f,
  * u = (sum f e + F/2) / rho (Sec. 3, "update hydrodynamic fields"), written

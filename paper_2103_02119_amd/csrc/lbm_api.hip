@@ -81,6 +81,7 @@ struct lbm_ctx {
     unsigned char *d_mask;        // obstacle mask [ny][pitch] (or null)
     unsigned char *d_tile_solid;  // per step tile: obstacle in its neighbourhood
     int steps_per_launch;         // 0 automatic, 1, 2 (lbm_set_steps_per_launch)
+    int two_step_form;            // kFormAuto, kFormRegister, kFormStaged
     double *scratch;              // device address of `scratch` on this context's GPU
     long steps;
     char err[512];
@@ -466,8 +467,7 @@ extern "C" int lbm_set_fields(lbm_ctx *c, const double *rho, const double *ux, c
 // Cache, so that a step is bound by HBM traffic; one otherwise.
 static int steps_per_launch(const lbm_ctx *c) {
     if (!uses_tile_kernel(c->G) || c->steps_per_launch == 1) return 1;
-    if (c->steps_per_launch == 2) return 2;
-    return c->G.nt_store ? 2 : 1;
+    return 2;
 }
 
 extern "C" int lbm_step(lbm_ctx *c, long n) {
@@ -483,8 +483,8 @@ extern "C" int lbm_step(lbm_ctx *c, long n) {
         const int src = c->cur, dst = 1 - c->cur;
         const bool pull = c->form[src] == kPost;
         const bool two = k == 2 && pull && left > last_single;
-        hipError_t e = two ? launch_step2(c->prec, c->coll, c->higher_unit, c->f[src], c->f[dst],
-                                          c->G, c->Kd, c->Kf, c->stream)
+        hipError_t e = two ? launch_step2(c->prec, c->coll, c->higher_unit, c->two_step_form,
+                                          c->f[src], c->f[dst], c->G, c->Kd, c->Kf, c->stream)
                            : launch_step(c->prec, c->coll, pull, c->higher_unit, c->f[src],
                                          c->f[dst], c->G, c->Kd, c->Kf, c->stream);
         if (e != hipSuccess)
@@ -508,6 +508,21 @@ extern "C" int lbm_set_steps_per_launch(lbm_ctx *c, int k) {
 extern "C" int lbm_steps_per_launch(const lbm_ctx *c) {
     if (!c) return LBM_E_INVAL;
     return steps_per_launch(c);
+}
+
+extern "C" int lbm_set_two_step_form(lbm_ctx *c, int form) {
+    if (!c) return fail_ctx(nullptr, LBM_E_INVAL, "ctx is NULL");
+    if (form != kFormAuto && form != kFormRegister && form != kFormStaged)
+        return fail_ctx(c, LBM_E_INVAL, "two-step form must be 0, 1 or 2");
+    if (form == kFormStaged && c->prec != kFP32Dev)
+        return fail_ctx(c, LBM_E_INVAL, "the staged two-step form needs LBM_FP32_DEV");
+    c->two_step_form = form;
+    return LBM_OK;
+}
+
+extern "C" int lbm_two_step_form(const lbm_ctx *c) {
+    if (!c) return LBM_E_INVAL;
+    return two_step_form(c->prec, c->two_step_form, c->G);
 }
 
 extern "C" int lbm_stream_copy(void *dst, const void *src, size_t bytes, int workgroups,

@@ -269,14 +269,21 @@ __device__ __forceinline__ void store_node(S *__restrict__ dst, const Geometry &
 // ------------------------------------------------------------ collision
 
 // 1-D inverse transform: central moments (k0, k1, k2) about velocity v of a
-// 3-velocity set {0, +1, -1} -> populations (p0, p+, p-).
+// 3-velocity set {0, +1, -1} -> populations (p0, p+, p-), with the raw
+// moments r1 = k1 + v k0, r2 = k2 + 2 v k1 + v^2 k0 and
+// p0 = k0 - r2, p+- = (r2 +- r1) / 2.  The first and second moments come
+// in halved (h1 = k1 / 2, h2 = k2 / 2) and so do v and v^2 where they scale
+// k0 (hv = v / 2, hv2 = v^2 / 2; tv = 2 v): the halves of r1 and r2 then give
+// p+- with one addition each.  Halving is exact in binary floating point,
+// so every result equals that of the unhalved form bit for bit.
 template <typename R>
-__device__ __forceinline__ void inv1d(R k0, R k1, R k2, R v, R v2, R &p0, R &pp, R &pm) {
-    const R r1 = k1 + v * k0;
-    const R r2 = k2 + R(2) * v * k1 + v2 * k0;
-    p0 = k0 - r2;
-    pp = R(0.5) * (r2 + r1);
-    pm = R(0.5) * (r2 - r1);
+__device__ __forceinline__ void inv1d(R k0, R h1, R h2, R hv, R hv2, R tv, R &p0, R &pp,
+                                      R &pm) {
+    const R g1 = h1 + hv * k0;               // r1 / 2
+    const R g2 = (h2 + tv * h1) + hv2 * k0;  // r2 / 2
+    p0 = k0 - R(2) * g2;
+    pp = g2 + g1;
+    pm = g2 - g1;
 }
 
 // Post-collision values o[9] of one node from its pre-collision values p[9]
@@ -393,7 +400,13 @@ __device__ __forceinline__ void collide_post(const R (&p)[9], const Pre<R> &q, R
         const R M4 = q.Q4 - tx + ty;
         const R b1 = K.b1c + R(1.5) * ux2, b2 = K.b2c + R(1.5) * uy2;
         const R c1 = K.c1c + R(1.5) * ux2, c2 = K.c2c - R(1.5) * uy2;
-        const R idet = q.irho / (b1 * c2 - c1 * b2);
+        // FP32: the hardware reciprocal (1 ulp) in place of an IEEE division,
+        // which costs about ten instructions per node
+        R idet;
+        if constexpr (sizeof(R) == 4)
+            idet = q.irho * __builtin_amdgcn_rcpf(b1 * c2 - c1 * b2);
+        else
+            idet = q.irho / (b1 * c2 - c1 * b2);
         const R X = (c2 * M3 - b2 * M4) * idet;  // d ux / dx
         const R Y = (b1 * M4 - c1 * M3) * idet;  // d uy / dy
         const R t1 = K.q1 * (rho * X + ux * gx);
@@ -474,23 +487,31 @@ __device__ __forceinline__ void collide_post(const R (&p)[9], const Pre<R> &q, R
         }
     }
 
-    // back to natural moments in (cx, cy) units
-    const R t20 = R(0.5) * (D3 + D4);
-    const R t02 = R(0.5) * (D3 - D4) * K.inv_a2;
-    const R t01 = D2 * K.inv_a, t11 = D5 * K.inv_a, t21 = D6 * K.inv_a;
-    const R t12 = D7 * K.inv_a2, t22 = D8 * K.inv_a2;
+    // back to natural moments t_mn in (cx, cy) units: t00 = D0, t10 = D1,
+    // t20 = (D3 + D4) / 2, t01 = D2 / a, t11 = D5 / a, t21 = D6 / a,
+    // t02 = (D3 - D4) / (2 a^2), t12 = D7 / a^2, t22 = D8 / a^2.
+    // The y stage takes t_m1, t_m2 halved; its outputs for m = 1, 2 are the
+    // x stage's first and second moments, so those two rows go in scaled by
+    // a further 1/2 (see inv1d).
+    const R h_a = R(0.5) * K.inv_a;
+    const R q_a = R(0.25) * K.inv_a, q_a2 = R(0.25) * K.inv_a2;
+    const R h01 = D2 * h_a, h02 = (D3 - D4) * q_a2;                        // m = 0
+    const R h10 = R(0.5) * D1, h11 = D5 * q_a, h12 = D7 * q_a2;             // m = 1, / 2
+    const R h20 = R(0.25) * (D3 + D4), h21 = D6 * q_a, h22 = D8 * q_a2;     // m = 2, / 2
     // RC: they are central moments about (ux, vy); RNR: raw (about 0)
     const R sx = (COLL == kRC) ? ux : R(0), sx2 = (COLL == kRC) ? ux2 : R(0);
     const R sy = (COLL == kRC) ? q.vy : R(0), sy2 = (COLL == kRC) ? q.vy2 : R(0);
+    const R hsx = R(0.5) * sx, hsx2 = R(0.5) * sx2, tsx = R(2) * sx;
+    const R hsy = R(0.5) * sy, hsy2 = R(0.5) * sy2, tsy = R(2) * sy;
     // y stage for m = 0, 1, 2
     R y00, y0p, y0m, y10, y1p, y1m, y20, y2p, y2m;
-    inv1d(D0, t01, t02, sy, sy2, y00, y0p, y0m);
-    inv1d(D1, t11, t12, sy, sy2, y10, y1p, y1m);
-    inv1d(t20, t21, t22, sy, sy2, y20, y2p, y2m);
-    // x stage for cy = 0, +1, -1
-    inv1d(y00, y10, y20, sx, sx2, o[0], o[1], o[3]);
-    inv1d(y0p, y1p, y2p, sx, sx2, o[2], o[5], o[6]);
-    inv1d(y0m, y1m, y2m, sx, sx2, o[4], o[8], o[7]);
+    inv1d(D0, h01, h02, hsy, hsy2, tsy, y00, y0p, y0m);
+    inv1d(h10, h11, h12, hsy, hsy2, tsy, y10, y1p, y1m);
+    inv1d(h20, h21, h22, hsy, hsy2, tsy, y20, y2p, y2m);
+    // x stage for cy = 0, +1, -1 (y1., y2. are halved moments)
+    inv1d(y00, y10, y20, hsx, hsx2, tsx, o[0], o[1], o[3]);
+    inv1d(y0p, y1p, y2p, hsx, hsx2, tsx, o[2], o[5], o[6]);
+    inv1d(y0m, y1m, y2m, hsx, hsx2, tsx, o[4], o[8], o[7]);
 }
 
 template <typename R, bool DEV, int COLL, bool HU>

@@ -144,8 +144,12 @@ hipError_t launch_march_step(int prec, int coll, bool pull, bool higher_unit, co
                              void *dst, const Geometry &G, const Consts<double> &Kd,
                              const Consts<float> &Kf, hipStream_t st);
 // two steps per launch (lbm_tile2.hip): src must hold post-collision values
-// (pull form) and the lattice no obstacle mask; dst receives step t+1
-hipError_t launch_step2(int prec, int coll, bool higher_unit, const void *src, void *dst,
+// (pull form) and the lattice no obstacle mask; dst receives step t+1.
+// form: kFormAuto, kFormRegister or kFormStaged (FP32 storage and arithmetic
+// only); two_step_form tells which one a launch takes.
+constexpr int kFormAuto = 0, kFormRegister = 1, kFormStaged = 2;
+int two_step_form(int prec, int form, const Geometry &G);
+hipError_t launch_step2(int prec, int coll, bool higher_unit, int form, const void *src, void *dst,
                         const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
                         hipStream_t st);
 // streaming copy of n16 16-byte words (the measured bandwidth ceiling);

@@ -17,25 +17,33 @@
 // (x0 .. x0+63, j0 .. j0+TY-1) the workgroup
 //   A  pulls the step-t pre-collision values of region Q = the tile grown by
 //      3 nodes (70 x (TY+6)) from the source buffer and puts each density in
-//      LDS; the values of the inner region P = the tile grown by 2 nodes
-//      (68 x (TY+4)) stay in registers (at most two nodes per thread);
-//   B  collides P (density gradient from LDS) and writes its post-collision
-//      values of step t to an LDS tile;
+//      LDS;
+//   B  collides the inner region P = the tile grown by 2 nodes (68 x (TY+4);
+//      density gradient from LDS) and writes its post-collision values of
+//      step t to an LDS tile;
 //   C  pulls the step-t+1 pre-collision values of the tile and its one-node
 //      density ring from that LDS tile (half-way bounce-back at walls) and
 //      puts the densities in LDS;
 //   D  collides the tile and stores step t+1 to the destination buffer.
-// Neighbouring tiles recompute the overlap of their P regions (30% more
-// collisions at TY = 8); their reads of the overlapping halo rows and
-// columns are served by L2 and the Infinity Cache.
+// Neighbouring tiles recompute the overlap of their P regions: (68 (TY+4) +
+// 64 TY) / (128 TY) collisions per lattice update, 1.30 at TY = 8 and 1.12
+// at TY = 24.  Their reads of the overlapping halo rows and columns are
+// served by L2 and the Infinity Cache.
+//
+// Two forms.  The register form (tile2_step_kernel, 64 TY threads) keeps
+// the step-t pre-collision values of P in registers from A to B (at most two
+// nodes per thread) and the step-t values in LDS in the storage type.  The
+// staged form (tile2_staged_kernel) also parks the pre-collision values of P
+// in the LDS tile, so no thread holds populations across a barrier and fewer
+// threads than nodes can cover a taller tile, which recomputes less overlap.
 //
 // Periodic faces are handled by computing halo nodes with wrapped
 // coordinates (the LDS tile is unwrapped, so steps B-D need no wrap), walls
 // by leaving out the nodes beyond them and bouncing back the links that
 // would come from there.  Every node goes through the same loaders,
 // collision and rounding as in the one-step kernels (the step-t values are
-// kept in LDS in the storage type), so two steps here equal two one-step
-// launches bit for bit.
+// rounded to the storage type before step t+1 reads them), so two steps here
+// equal two one-step launches bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "lbm_device.h"
@@ -281,6 +289,178 @@ __device__ __forceinline__ void tile2_body(const S *__restrict__ src, S *__restr
 #undef load
 }
 
+// Staged form: the step-t pre-collision values of P wait in the LDS tile
+// (each P node's slots are then overwritten by its own post-collision values
+// in B), and NT threads cover a 64 x TY tile, TY * 64 / NT output rows per
+// thread.  The tile holds the values in the arithmetic type; the
+// post-collision ones are rounded to the storage type first, as if they had
+// been stored and reloaded.
+template <int TY, int NT>
+struct T2S {
+    static constexpr int OW = kWave;
+    static constexpr int PW = OW + 4, PH = TY + 4;      // region P
+    static constexpr int QW = OW + 6, QH = TY + 6;      // region Q
+    static constexpr int CW = OW + 2, CH = TY + 2;      // tile + ring
+    static constexpr int NQ = QW * QH, NP = PW * PH;
+    static constexpr int QPER = (NQ + NT - 1) / NT;     // Q nodes per thread
+    static constexpr int PPER = (NP + NT - 1) / NT;     // P nodes per thread
+    static constexpr int WAVES = NT / kWave;
+    static constexpr int RPT = TY / WAVES;              // output rows per thread
+    static constexpr int NCR = 2 * CW + 2 * TY;         // ring nodes of the tile
+    static_assert(NT % kWave == 0 && TY % WAVES == 0, "whole output rows per wavefront");
+    static_assert(NCR <= NT, "one ring node per thread");
+};
+
+template <typename S, typename R, bool DEV, int COLL, bool HU, int TY, int NT, int LOAD, bool WALLS>
+__device__ __forceinline__ void tile2_body_staged(const S *__restrict__ src, S *__restrict__ dst,
+                                                  const Geometry &G, const Consts<R> &K, int x0,
+                                                  int j0, R (*pb)[T2S<TY, NT>::PH][T2S<TY, NT>::PW],
+                                                  R (*r1)[T2S<TY, NT>::QW],
+                                                  R (*r2)[T2S<TY, NT>::CW]) {
+    using C = T2S<TY, NT>;
+    const int t = static_cast<int>(threadIdx.x);
+
+#define at(xx, jj) node_in<LOAD>(xx, jj, G)
+#define load(xx, jj, f) load_any<S, R, LOAD>(src, G, K, xx, jj, f)
+
+    // ---- A: every Q node's step-t pre-collision values (all loads first),
+    // its density to r1 and, inside P, its values to the LDS tile
+    R f[C::QPER][9];
+    bool ok[C::QPER];
+#pragma unroll
+    for (int i = 0; i < C::QPER; ++i) {
+        const int q = t + i * NT;
+        const int qx = q % C::QW, qy = q / C::QW;
+        const NodeAt n = at(x0 - 3 + qx, j0 - 3 + qy);
+        ok[i] = q < C::NQ && (LOAD == 0 || n.in);
+        if (ok[i]) load(n.x, n.j, f[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < C::QPER; ++i) {
+        const int q = t + i * NT;
+        if (q < C::NQ) {
+            const int qx = q % C::QW, qy = q / C::QW;
+            r1[qy][qx] = ok[i] ? sum9(f[i]) : R(0);
+            if (ok[i] && qx >= 1 && qx <= C::PW && qy >= 1 && qy <= C::PH) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) pb[k][qy - 1][qx - 1] = f[i][k];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- B: collide P in place, step-t post-collision values to the LDS tile
+#pragma unroll
+    for (int i = 0; i < C::PPER; ++i) {
+        const int p = t + i * NT;
+        const int px = p % C::PW, py = p / C::PW;
+        const NodeAt n = at(x0 - 2 + px, j0 - 2 + py);
+        if (p < C::NP && (LOAD == 0 || n.in)) {
+            R v[9], o[9], gx, gy;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) v[k] = pb[k][py][px];
+            gradient<R, C::QW, WALLS>(r1, px + 1, py + 1, r1[py + 1][px + 1], n.x, n.j, G, K, gx,
+                                      gy);
+            const Pre<R> pr = collide_pre<R, DEV, COLL>(v, K);
+            collide_post<R, DEV, COLL, HU>(v, pr, gx, gy, G.corr, K, o);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) pb[k][py][px] = static_cast<R>(static_cast<S>(o[k]));
+        }
+    }
+    __syncthreads();
+
+    // ---- C: step-t+1 pre-collision values of the tile's rows of this thread
+    // (registers) and the densities of the tile and its ring (r2 in the space
+    // of r1)
+    const int tx = t & (kWave - 1);
+    const int tw = t >> 6;
+    R g[C::RPT][9], rco[C::RPT];
+#pragma unroll
+    for (int r = 0; r < C::RPT; ++r) {
+        const int ty = tw + r * C::WAVES;
+        const NodeAt no = at(x0 + tx, j0 + ty);
+        rco[r] = R(0);
+        if (LOAD == 0 || no.in) {
+            pull_lds<R, R, C::PW, C::PH, WALLS>(pb, tx + 2, ty + 2, no.x, no.j, G, K, g[r]);
+            rco[r] = sum9(g[r]);
+        }
+    }
+    int cx = 0, cy = 0;
+    if (t < C::CW) {
+        cx = t;
+        cy = 0;
+    } else if (t < 2 * C::CW) {
+        cx = t - C::CW;
+        cy = C::CH - 1;
+    } else if (t < 2 * C::CW + TY) {
+        cx = 0;
+        cy = 1 + t - 2 * C::CW;
+    } else {
+        cx = C::CW - 1;
+        cy = 1 + t - 2 * C::CW - TY;
+    }
+    const bool hasc = t < C::NCR;
+    const NodeAt nc = at(x0 - 1 + cx, j0 - 1 + cy);
+    R rcr = R(0);
+    if (hasc && (LOAD == 0 || nc.in)) {
+        R h[9];
+        pull_lds<R, R, C::PW, C::PH, WALLS>(pb, cx + 1, cy + 1, nc.x, nc.j, G, K, h);
+        rcr = sum9(h);
+    }
+    // r2 aliases r1: every read of r1 (step B) is behind the last barrier
+#pragma unroll
+    for (int r = 0; r < C::RPT; ++r) r2[tw + r * C::WAVES + 1][tx + 1] = rco[r];
+    if (hasc) r2[cy][cx] = rcr;
+    __syncthreads();
+
+    // ---- D: collide the tile's rows of this thread, step t+1 to the
+    // destination buffer
+#pragma unroll
+    for (int r = 0; r < C::RPT; ++r) {
+        const int ty = tw + r * C::WAVES;
+        const int ox = x0 + tx, oj = j0 + ty;
+        const NodeAt no = at(ox, oj);
+        if (ox < G.nx && oj < G.ny && (LOAD == 0 || no.in)) {
+            R gx, gy, o[9];
+            gradient<R, C::CW, WALLS>(r2, tx + 1, ty + 1, rco[r], no.x, no.j, G, K, gx, gy);
+            const Pre<R> pr = collide_pre<R, DEV, COLL>(g[r], K);
+            collide_post<R, DEV, COLL, HU>(g[r], pr, gx, gy, G.corr, K, o);
+            store_node(dst, G, oj, ox, o);
+        }
+    }
+#undef at
+#undef load
+}
+
+template <typename S, typename R, bool DEV, int COLL, bool HU, int TY, int NT, int WPE>
+__global__ void __launch_bounds__(NT, WPE)
+tile2_staged_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
+                    const Consts<R> K, int ntx, int nty) {
+    using C = T2S<TY, NT>;
+    __shared__ R pb[9][C::PH][C::PW];
+    __shared__ R rr[C::QH * C::QW];
+    int b = blockIdx.x;
+    const int nb = static_cast<int>(gridDim.x);
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
+    if (b >= ntx * nty) return;                             // padding workgroup (whole block)
+    const int x0 = (b % ntx) * kWave, j0 = (b / ntx) * TY;
+    R(*r1)[C::QW] = reinterpret_cast<R(*)[C::QW]>(rr);
+    R(*r2)[C::CW] = reinterpret_cast<R(*)[C::CW]>(rr);
+    const bool walls = G.bc[kXmin] != kPeriodic || G.bc[kYmin] != kPeriodic;
+    const bool rows_in = G.buf_ok && j0 >= 4 && j0 + TY + 4 <= G.ny;
+    const bool cols_in = x0 >= 4 && x0 + kWave + 4 <= G.nx;
+    if (rows_in && cols_in)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 0, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else if (rows_in && !walls)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 1, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else if (rows_in)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 1, true>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else if (walls)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, true>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+}
+
 template <typename S, typename R, bool DEV, int COLL, bool HU, int TY>
 __global__ void __launch_bounds__(kWave * TY)
 tile2_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
@@ -312,24 +492,70 @@ tile2_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry
         tile2_body<S, R, DEV, COLL, HU, TY, 2, false>(src, dst, G, K, x0, j0, pb, r1, r2);
 }
 
-// Rows of the output tile.  Measured on the 2048 x 8192 lattice (FP32
-// storage and arithmetic, per pair of steps): 64 x 16 tiles (1024 threads,
-// one workgroup per CU by its registers) 442 us, the same with the
-// compiler held to two workgroups per CU 351 us, 64 x 8 tiles (512 threads,
-// three workgroups per CU) 341 us.  FP64 takes 64 x 8 too: its step-t tile
-// in LDS (67 KB) leaves room for two workgroups per CU.
+// Rows of the register form's output tile.  Measured on the 2048 x 8192
+// lattice (FP32 storage and arithmetic, per pair of steps): 64 x 16 tiles
+// (1024 threads, one workgroup per CU by its registers) 442 us, the same
+// with the compiler held to two workgroups per CU 351 us, 64 x 8 tiles (512
+// threads, three workgroups per CU) 341 us.  FP64 takes 64 x 8 too: its
+// step-t tile in LDS (67 KB) leaves room for two workgroups per CU, and a
+// taller staged tile in FP64 would leave room for one.
 template <typename R>
 constexpr int tile2_rows() { return 8; }
 
+// Tile of the staged form with FP32 storage and arithmetic: rows, threads
+// and the waves per SIMD asked of the compiler (0 rows: the register form
+// for every type).  Measured on the same lattice, per pair of steps, with
+// the same collision code (two runs; 64 x 16, timed in both, gave 309-311
+// us in each): 64 x 8 register form 336-338 us; staged 64 x 12 / 384
+// threads 346, 64 x 14 / 448 328, 64 x 16 / 512 309-311, 64 x 18 / 576 467,
+// 64 x 20 / 640 439, 64 x 24 / 768 285 (77 KB of LDS, two workgroups per
+// CU), 64 x 32 / 1024 380 (one workgroup per CU).
+constexpr int kStagedRows = 24, kStagedThreads = 768, kStagedWaves = 6;
+
+// The automatic choice takes the staged form from this many of its
+// workgroups up (four per CU).  Its fixed cost per launch is higher (7-8 us
+// per step on lattices of up to 256 x 512 nodes, against 4.5-5 us), so
+// smaller lattices run the register form: measured per step with cavity
+// boundaries, register / staged, 512 x 1024 9.2 / 9.7 us, 1024 x 1024 (688
+// staged workgroups) 13.0 / 13.0, 1024 x 2048 (1376) 20.9 / 19.6, 2048 x 4096
+// 89.4 / 77.1.
+constexpr int kStagedMinGroups = 1024;
+
+int staged_groups(const Geometry &G) {
+    return ((G.nx + kWave - 1) / kWave) * ((G.ny + kStagedRows - 1) / kStagedRows);
+}
+
 template <typename S, typename R, bool DEV>
-hipError_t tile2_dispatch(int coll, bool hu, const void *src, void *dst, const Geometry &G,
-                          const Consts<R> &K, hipStream_t st) {
+hipError_t staged_dispatch(int coll, bool hu, const S *s, S *d, const Geometry &G,
+                           const Consts<R> &K, hipStream_t st) {
+    constexpr int TY = kStagedRows, NT = kStagedThreads, WPE = kStagedWaves;
+    const int ntx = (G.nx + kWave - 1) / kWave, nty = (G.ny + TY - 1) / TY;
+    const int n = ntx * nty;
+    const dim3 grid((n + 7) / 8 * 8), block(NT);
+#define LBM_T2S(CO, H) \
+    hipLaunchKernelGGL((tile2_staged_kernel<S, R, DEV, CO, H, TY, NT, WPE>), grid, block, 0, st, s, d, G, K, ntx, nty)
+    if (coll == kRC) {
+        if (hu) LBM_T2S(kRC, true); else LBM_T2S(kRC, false);
+    } else {
+        if (hu) LBM_T2S(kRNR, true); else LBM_T2S(kRNR, false);
+    }
+#undef LBM_T2S
+    return hipGetLastError();
+}
+
+template <typename S, typename R, bool DEV>
+hipError_t tile2_dispatch(int coll, bool hu, int form, const void *src, void *dst,
+                          const Geometry &G, const Consts<R> &K, hipStream_t st) {
+    const S *s = static_cast<const S *>(src);
+    S *d = static_cast<S *>(dst);
+    if constexpr (sizeof(R) == 4 && sizeof(S) == 4) {
+        if (form == kFormStaged) return staged_dispatch<S, R, DEV>(coll, hu, s, d, G, K, st);
+    }
+    if (form == kFormStaged) return hipErrorInvalidValue;
     constexpr int TY = tile2_rows<R>();
     const int ntx = (G.nx + kWave - 1) / kWave, nty = (G.ny + TY - 1) / TY;
     const int n = ntx * nty;
     const dim3 grid((n + 7) / 8 * 8), block(kWave * TY);
-    const S *s = static_cast<const S *>(src);
-    S *d = static_cast<S *>(dst);
 #define LBM_T2(CO, H) \
     hipLaunchKernelGGL((tile2_step_kernel<S, R, DEV, CO, H, TY>), grid, block, 0, st, s, d, G, K, ntx, nty)
     if (coll == kRC) {
@@ -343,13 +569,22 @@ hipError_t tile2_dispatch(int coll, bool hu, const void *src, void *dst, const G
 
 }  // namespace
 
-hipError_t launch_step2(int prec, int coll, bool hu, const void *src, void *dst, const Geometry &G,
-                        const Consts<double> &Kd, const Consts<float> &Kf, hipStream_t st) {
+int two_step_form(int prec, int form, const Geometry &G) {
+    if (prec != kFP32Dev) return kFormRegister;  // the staged form is FP32 only
+    if (form != kFormAuto) return form;
+    return staged_groups(G) >= kStagedMinGroups ? kFormStaged : kFormRegister;
+}
+
+hipError_t launch_step2(int prec, int coll, bool hu, int form, const void *src, void *dst,
+                        const Geometry &G, const Consts<double> &Kd, const Consts<float> &Kf,
+                        hipStream_t st) {
+    if (form == kFormStaged && prec != kFP32Dev) return hipErrorInvalidValue;
+    const int f = two_step_form(prec, form, G);
     switch (prec) {
-    case kFP64: return tile2_dispatch<double, double, false>(coll, hu, src, dst, G, Kd, st);
-    case kFP32Dev: return tile2_dispatch<float, float, true>(coll, hu, src, dst, G, Kf, st);
-    case kFP64Dev: return tile2_dispatch<double, double, true>(coll, hu, src, dst, G, Kd, st);
-    case kFP32DevF64: return tile2_dispatch<float, double, true>(coll, hu, src, dst, G, Kd, st);
+    case kFP64: return tile2_dispatch<double, double, false>(coll, hu, f, src, dst, G, Kd, st);
+    case kFP32Dev: return tile2_dispatch<float, float, true>(coll, hu, f, src, dst, G, Kf, st);
+    case kFP64Dev: return tile2_dispatch<double, double, true>(coll, hu, f, src, dst, G, Kd, st);
+    case kFP32DevF64: return tile2_dispatch<float, double, true>(coll, hu, f, src, dst, G, Kd, st);
     default: return hipErrorInvalidValue;
     }
 }

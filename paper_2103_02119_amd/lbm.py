@@ -24,9 +24,11 @@ LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_MOVING_WALL = 0, 1, 2
 LBM_FACE_XMIN, LBM_FACE_XMAX, LBM_FACE_YMIN, LBM_FACE_YMAX = 0, 1, 2, 3
 LBM_RC, LBM_RNR = 0, 1
 LBM_FP64, LBM_FP32_DEV, LBM_FP64_DEV, LBM_FP32_DEV_F64 = 0, 1, 2, 3
+LBM_FORM_AUTO, LBM_FORM_REGISTER, LBM_FORM_STAGED = 0, 1, 2
 
 EXPORTS = ("lbm_default_opts", "lbm_required_bytes", "lbm_create", "lbm_set_fields", "lbm_step",
-           "lbm_set_steps_per_launch", "lbm_steps_per_launch",
+           "lbm_set_steps_per_launch", "lbm_steps_per_launch", "lbm_set_two_step_form",
+           "lbm_two_step_form",
            "lbm_moments", "lbm_stress", "lbm_residual", "lbm_sums", "lbm_check_async",
            "lbm_check_result", "lbm_check_into", "lbm_get_populations", "lbm_set_populations",
            "lbm_set_mask", "lbm_set_rates", "lbm_set_force", "lbm_step_forced", "lbm_smooth_step",
@@ -127,6 +129,10 @@ def load():
     L.lbm_set_steps_per_launch.restype = ctypes.c_int
     L.lbm_steps_per_launch.argtypes = [_CTX]
     L.lbm_steps_per_launch.restype = ctypes.c_int
+    L.lbm_set_two_step_form.argtypes = [_CTX, ctypes.c_int]
+    L.lbm_set_two_step_form.restype = ctypes.c_int
+    L.lbm_two_step_form.argtypes = [_CTX]
+    L.lbm_two_step_form.restype = ctypes.c_int
     L.lbm_check_into.argtypes = [_CTX, ctypes.c_void_p]
     L.lbm_check_into.restype = ctypes.c_int
     L.lbm_stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
@@ -269,6 +275,17 @@ def lbm_steps_per_launch(ctx) -> int:
     if k < 0:
         raise LbmError(k, "NULL context")
     return k
+
+
+def lbm_set_two_step_form(ctx, form: int):
+    _check(load().lbm_set_two_step_form(ctx, int(form)), ctx)
+
+
+def lbm_two_step_form(ctx) -> int:
+    f = load().lbm_two_step_form(ctx)
+    if f < 0:
+        raise LbmError(f, "NULL context")
+    return f
 
 
 def lbm_moments(ctx, nx, ny):
@@ -431,6 +448,12 @@ class Lattice:
 
     def steps_per_launch(self):
         return lbm_steps_per_launch(self.ctx)
+
+    def set_two_step_form(self, form):
+        lbm_set_two_step_form(self.ctx, form)
+
+    def two_step_form(self):
+        return lbm_two_step_form(self.ctx)
 
     def check_into(self, out_ptr):
         lbm_check_into(self.ctx, out_ptr)

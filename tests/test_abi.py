@@ -212,11 +212,13 @@ def test_null_handles_are_rejected_before_touching_the_device():
         "lbm_step_forced": (None, 1, pd, pd),
         "lbm_smooth_step": (None,),
         "lbm_set_steps_per_launch": (None, 1),
+        "lbm_set_two_step_form": (None, 1),
         "lbm_check_into": (None, None),
     }
     for name, args in calls.items():
         assert getattr(lib, name)(*args) == L.LBM_E_INVAL, name
     assert lib.lbm_steps_per_launch(None) == L.LBM_E_INVAL
+    assert lib.lbm_two_step_form(None) == L.LBM_E_INVAL
     assert lib.lbm_destroy(None) == L.LBM_OK
     assert lib.lbm_batch_step(None, 1) == L.LBM_E_INVAL
     assert lib.lbm_batch_destroy(None) == L.LBM_OK

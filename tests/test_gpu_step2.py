@@ -19,14 +19,21 @@ from test_gpu_parity import CASES, RATES_GEN, RATES_HU, TOL64, announce, make, r
 pytestmark = pytest.mark.gpu
 
 PRECS = [L.LBM_FP64, L.LBM_FP32_DEV, L.LBM_FP64_DEV, L.LBM_FP32_DEV_F64]
+REG, STAGED = L.LBM_FORM_REGISTER, L.LBM_FORM_STAGED
+# (precision, two-step form): the register form in every precision, the
+# staged form (FP32 storage and arithmetic only) beside it
+PREC_FORMS = [(p, REG) for p in PRECS] + [(L.LBM_FP32_DEV, STAGED)]
 
 
-def pair(name, nx, ny, coll, prec, rates=RATES_HU, corr=True):
-    """Two lattices with the same parameters: one step per launch, two."""
+def pair(name, nx, ny, coll, prec, rates=RATES_HU, corr=True, form=REG):
+    """Two lattices with the same parameters: one step per launch, two (in
+    the given form of the two-step kernel)."""
     p, one = make(name, nx, ny, coll, prec, rates=rates, corr=corr)
     _, two = make(name, nx, ny, coll, prec, rates=rates, corr=corr)
     one.set_steps_per_launch(1)
     two.set_steps_per_launch(2)
+    two.set_two_step_form(form)
+    assert two.two_step_form() == form
     return p, one, two
 
 
@@ -40,13 +47,13 @@ def same_after(p, one, two, n, seed=2103):
     return a, b, f0
 
 
-@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("prec,form", PREC_FORMS)
 @pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
 @pytest.mark.parametrize("name", list(CASES))
-def test_two_steps_per_launch_bit_identical(name, coll, prec):
+def test_two_steps_per_launch_bit_identical(name, coll, prec, form):
     nx, ny = 150, 70  # interior, x-face and y-face tiles, ragged last column of tiles
-    announce("step2", name, coll, prec, nx, ny)
-    p, one, two = pair(name, nx, ny, coll, prec)
+    announce("step2", name, coll, prec, form, nx, ny)
+    p, one, two = pair(name, nx, ny, coll, prec, form=form)
     assert two.steps_per_launch() == 2 and one.steps_per_launch() == 1
     a, b, _ = same_after(p, one, two, 7)  # one step from the set state, then three pairs
     assert np.array_equal(a, b), (name, coll, prec, float(np.abs(a - b).max()))
@@ -54,28 +61,30 @@ def test_two_steps_per_launch_bit_identical(name, coll, prec):
     two.close()
 
 
-@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+@pytest.mark.parametrize("prec,form", [(L.LBM_FP64, REG), (L.LBM_FP32_DEV, REG),
+                                       (L.LBM_FP32_DEV, STAGED)])
 @pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
 @pytest.mark.parametrize("name", ["periodic", "cavity", "xmoving"])
-def test_two_steps_general_rates_and_no_corrections(name, coll, prec):
+def test_two_steps_general_rates_and_no_corrections(name, coll, prec, form):
     nx, ny = 97, 45
     for rates, corr in ((RATES_GEN, True), (RATES_HU, False), (RATES_GEN, False)):
-        announce("step2", name, coll, prec, rates, corr)
-        p, one, two = pair(name, nx, ny, coll, prec, rates=rates, corr=corr)
+        announce("step2", name, coll, prec, form, rates, corr)
+        p, one, two = pair(name, nx, ny, coll, prec, rates=rates, corr=corr, form=form)
         a, b, _ = same_after(p, one, two, 5, seed=7)
         assert np.array_equal(a, b), (name, rates, corr)
         one.close()
         two.close()
 
 
-@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+@pytest.mark.parametrize("prec,form", [(L.LBM_FP64, REG), (L.LBM_FP32_DEV, REG),
+                                       (L.LBM_FP32_DEV, STAGED)])
 @pytest.mark.parametrize("shape", [(3, 3), (4, 3), (3, 5), (7, 4), (64, 4), (65, 6), (128, 3),
-                                   (130, 9), (200, 17), (72, 24), (300, 41)])
+                                   (130, 9), (200, 17), (72, 24), (300, 41), (70, 25), (129, 49)])
 @pytest.mark.parametrize("name", ["periodic", "cavity", "xwalls", "channel"])
-def test_two_steps_degenerate_shapes(name, shape, prec):
+def test_two_steps_degenerate_shapes(name, shape, prec, form):
     nx, ny = shape
-    announce("step2", name, shape, prec)
-    p, one, two = pair(name, nx, ny, 0, prec)
+    announce("step2", name, shape, prec, form)
+    p, one, two = pair(name, nx, ny, 0, prec, form=form)
     a, b, _ = same_after(p, one, two, 5, seed=11)
     assert np.array_equal(a, b), (name, shape, prec)
     one.close()
@@ -106,7 +115,9 @@ def test_step_counts_and_the_state_one_step_back():
     turns the two-step kernel off."""
     p, lat = make("cavity", 96, 40, 0, L.LBM_FP64)
     lat.set_fields(*I.random_fields(3, 96, 40))
-    assert lat.steps_per_launch() == 1  # small lattice: automatic = one
+    assert lat.steps_per_launch() == 2  # automatic: two on any lattice without a mask
+    lat.set_steps_per_launch(1)
+    assert lat.steps_per_launch() == 1
     lat.set_steps_per_launch(2)
     assert lat.steps_per_launch() == 2
     lat.step(1)
@@ -129,27 +140,54 @@ def test_step_counts_and_the_state_one_step_back():
     assert lat.steps_per_launch() == 1
     lat.set_mask(None)
     lat.set_steps_per_launch(0)
-    assert lat.steps_per_launch() == 1
+    assert lat.steps_per_launch() == 2
     with pytest.raises(L.LbmError):
         lat.set_steps_per_launch(3)
     lat.close()
 
 
-@pytest.mark.parametrize("prec", [L.LBM_FP32_DEV, L.LBM_FP64])
-def test_full_size_shear_layer_two_steps_bit_identical(prec):
-    """The 2048 x 8192, a = 0.25 shear layer (buffers beyond the Infinity
-    Cache, so the automatic choice takes two steps per launch) against one
-    step per launch."""
+def test_two_step_form_choice_and_validation():
+    """The automatic form: staged for FP32 storage from 1024 of its 64 x 24
+    tiles up, register below and in every other precision; the staged form
+    cannot be asked of another precision."""
+    for (nx, ny, prec), want in (((150, 70, L.LBM_FP32_DEV), REG),
+                                 ((1024, 1024, L.LBM_FP32_DEV), REG),     # 688 tiles
+                                 ((2048, 768, L.LBM_FP32_DEV), STAGED),   # 1024 tiles
+                                 ((2048, 768, L.LBM_FP64), REG),
+                                 ((2048, 768, L.LBM_FP32_DEV_F64), REG)):
+        p, lat = make("periodic", nx, ny, 0, prec)
+        assert lat.two_step_form() == want, (nx, ny, prec)
+        if prec != L.LBM_FP32_DEV:
+            with pytest.raises(L.LbmError) as e:
+                lat.set_two_step_form(STAGED)
+            assert e.value.code == L.LBM_E_INVAL
+        with pytest.raises(L.LbmError) as e:
+            lat.set_two_step_form(3)
+        assert e.value.code == L.LBM_E_INVAL
+        lat.set_two_step_form(REG)
+        assert lat.two_step_form() == REG
+        lat.close()
+
+
+@pytest.mark.parametrize("prec,form,want", [(L.LBM_FP32_DEV, L.LBM_FORM_AUTO, STAGED),
+                                            (L.LBM_FP32_DEV, REG, REG),
+                                            (L.LBM_FP64, L.LBM_FORM_AUTO, REG)])
+def test_full_size_shear_layer_two_steps_bit_identical(prec, form, want):
+    """The 2048 x 8192, a = 0.25 shear layer (the automatic choice takes two
+    steps per launch, in FP32 storage the staged form) against one step per
+    launch."""
     nx, ny, a, cs2, nu = 2048, 8192, 0.25, 0.04, 6e-3
     tau = nu / cs2 + 0.5
     rates = [1, 1, 1, 1, 1 / tau, 1 / tau, 1, 1, 1]
-    announce("step2 shear 2048x8192", prec)
+    announce("step2 shear 2048x8192", prec, form)
     fields = I.shear_layer(nx, ny, a, u0=0.04)
     out = []
     for k in (0, 1):
         lat = L.Lattice(nx, ny, a, rates, cs2=cs2, precision=prec)
         lat.set_steps_per_launch(k)
+        lat.set_two_step_form(form)
         assert lat.steps_per_launch() == (2 if k == 0 else 1)
+        assert lat.two_step_form() == want
         lat.set_fields(*fields)
         lat.step(6)  # one step from the set state, two pairs, one step
         lat.residual()
