@@ -280,6 +280,7 @@ def roofline_of(r, copy_gbs, traffic=None):
         "traffic": traffic[0] if traffic else None,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "traffic_over_algorithmic": traffic[1] if traffic else None,
+        "valu_issue": valu_ceiling_of(r, traffic[2] if traffic else None),
         "kernel": r["kernel"],
         "steps_per_launch": k,
         "algorithmic_bytes_per_launch": bpl,
@@ -317,8 +318,26 @@ def traffic_of(key):
         tr = json.load(fh)
     if tr.get("kernel_sha") == kernel_sha() and key in tr.get("per_launch", {}):
         e = tr["per_launch"][key]
-        return e["bytes_per_launch"], e["ratio"]
+        return e["bytes_per_launch"], e["ratio"], e.get("valu_insts_per_64_lu")
     return None
+
+
+# one wave64 vector instruction per CU per cycle (four SIMDs of 16 lanes)
+N_CU, CLOCK_GHZ = 256, 2.4
+
+
+def valu_ceiling_of(r, valu_per_64):
+    """The kernel's vector-ALU issue ceiling in lattice updates per second:
+    256 CUs x 2.4 GHz x one wave64 instruction per CU per cycle, over the
+    VALU instructions per lattice update that the counters measured."""
+    if not valu_per_64:
+        return None
+    peak = N_CU * CLOCK_GHZ * 1e9 / (valu_per_64 / 64) / 1e9  # GLUPS
+    got = r["steps_per_launch"] * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
+    return {"bound": "alu", "unit": "GLUPS", "achieved": round(got, 1), "peak": round(peak, 1),
+            "frac": round(got / peak, 4), "valu_insts_per_64_lu": valu_per_64,
+            "peak_from": "256 CUs x 2.4 GHz x one wave64 VALU instruction per CU per cycle "
+                         "(unpacked), over SQ_INSTS_VALU per lattice update (profiles/)"}
 
 
 def cpu_baseline(name, collision, budget_s=10.0):
@@ -379,6 +398,7 @@ def cavity_steady(tol=1e-8, check_every=10_000, cap=2_000_000):
         if R <= tol:
             break
     wall = time.perf_counter() - t0
+    progress(f"cavity fp64 from rest: residual {R:.2e} after {steps} steps, {wall:.1f} s")
     _, ux64, uy64 = lat.moments()
     lat.close()
     umax = float(np.hypot(ux64, uy64).max())
@@ -398,6 +418,11 @@ def cavity_steady(tol=1e-8, check_every=10_000, cap=2_000_000):
                                                  reference="the FP64 run of the same length")
 
 
+def progress(msg):
+    """A line on stderr as each stage of the benchmark ends."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def warm_start_section(n_cases=64, max_steps=400_000):
     """The learned warm start on unseen 256 x 128 cavities with obstacles
     (seeded Re in [100, 5000], a in {0.25, 0.5, 1}): steps and wall time to
@@ -409,7 +434,7 @@ def warm_start_section(n_cases=64, max_steps=400_000):
     if not os.path.exists(WS.WEIGHTS):
         return dict(warm_steps=None, reason=f"no trained weights at {WS.WEIGHTS}")
     cmp = WS.evaluate(WS.WEIGHTS, n_test=n_cases, max_steps=max_steps,
-                      modes=("cold", "cold+smooth", "warm+smooth"), log=lambda m: None)
+                      modes=("cold", "cold+smooth", "warm+smooth"), log=progress)
     ws, cs, cold = cmp["warm+smooth"], cmp["cold+smooth"], cmp["cold"]
     own = cmp["network_gain_warm+smooth_vs_cold+smooth"]
     return dict(workload=f"{n_cases} unseen 256x128 lid-driven cavities with obstacles, "
@@ -443,7 +468,6 @@ def bench_sweep(args):
     from paper_2103_02119_amd import workloads as W
 
     prec = L.LBM_FP32_DEV if args.precision == "fp32dev" else L.LBM_FP64
-    bytes_per_lu = 72 if prec == L.LBM_FP32_DEV else 144
     params = I.batch_sweep()
     cases = W.sweep_cases(params)
     nodes = sum(c.nx * c.ny for c in cases)
@@ -451,6 +475,10 @@ def bench_sweep(args):
     b = L.Batch(cases, precision=prec, graph_steps=args.graph_steps, stream=stream.cuda_stream)
     rows, wgs = b.autotune(5)
     tile = b.uses_tile_kernel()
+    spl = b.steps_per_launch()
+    # one step moves 9 values in and out per node; a two-step launch moves
+    # them once for two steps (the call's last one or two steps are single)
+    bytes_per_lu = (72 if prec == L.LBM_FP32_DEV else 144) // spl
     steps = (args.steps + args.graph_steps - 1) // args.graph_steps * args.graph_steps
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -487,10 +515,15 @@ def bench_sweep(args):
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "algorithmic_bytes_per_launch": bytes_per_lu * nodes,
-            "kernel": "lbm::batch_tile_kernel" if tile else "lbm::batch_step_kernel",
+            "algorithmic_bytes_per_launch": bytes_per_lu * nodes * spl,
+            "kernel": ("lbm::batch_tile2_kernel" if spl == 2 else
+                       "lbm::batch_tile_kernel" if tile else "lbm::batch_step_kernel"),
+            "steps_per_launch": spl,
             "bytes_per_lu": bytes_per_lu,
-            "kernel_us": round(1e3 * kern_ms, 3),
+            "kernel_us": round(1e3 * kern_ms * spl, 3),
+            "kernel_time_from": "HIP events around the timed call (graph replays of the "
+                                "batched launches; with two steps per launch the call's "
+                                "last one or two steps are single), per step x steps per launch",
         },
         "unstable_cases": int(np.isnan(R).sum()),
     }
@@ -555,12 +588,59 @@ def copy_probe_main(nbytes=1 << 30, reps=20):
                       "ms": round(ms, 4), "dispatches": reps + 1}), flush=True)
 
 
+SIZES = [(64, 32), (128, 256), (256, 512), (512, 1024), (1024, 1024), (1024, 2048),
+         (2048, 2048), (2048, 4096)]
+
+
+def bench_sizes():
+    """Microseconds per step of lid-driven cavities (a = 0.5, cs2 0.16, tau
+    0.625, FP32 deviations and FP64) for one step per launch and for two
+    steps per launch in each form of the two-step kernel (the staged form
+    in FP32 only); best of three runs of back-to-back launches, HIP events
+    on the library's stream.  One JSON line."""
+    import torch
+
+    from paper_2103_02119_amd import inputs as I
+    from paper_2103_02119_amd import lbm as L
+
+    out = {"workload": "cavities, a=0.5, cs2=0.16, tau=0.625, from rest; us per step", "sizes": {}}
+    for pname, prec in (("fp32dev", L.LBM_FP32_DEV), ("fp64", L.LBM_FP64)):
+        for nx, ny in SIZES:
+            steps = min(4000, max(200, int(4e9 / (nx * ny)) // 2 * 2))
+            row = {}
+            modes = [("one_step", 1, L.LBM_FORM_AUTO), ("two_step_register", 2, L.LBM_FORM_REGISTER)]
+            if prec == L.LBM_FP32_DEV:
+                modes.append(("two_step_staged", 2, L.LBM_FORM_STAGED))
+            for name, spl, form in modes:
+                lat = L.Lattice(nx, ny, 0.5, [1, 1, 1, 1, 1.6, 1.6, 1, 1, 1], bc_types=(1, 1, 1, 2),
+                                u_wall=((0, 0), (0, 0), (0, 0), (0.05, 0)), cs2=0.16,
+                                precision=prec)
+                lat.set_fields(*I.cavity_rest(nx, ny))
+                lat.set_two_step_form(form)
+                lat.step(101)
+                best = min(time_launches(lat, spl, steps // spl) for _ in range(3)) / spl
+                row[name] = round(1e3 * best, 3)
+                lat.close()
+            lat = L.Lattice(nx, ny, 0.5, [1, 1, 1, 1, 1.6, 1.6, 1, 1, 1], bc_types=(1, 1, 1, 2),
+                            u_wall=((0, 0), (0, 0), (0, 0), (0.05, 0)), cs2=0.16, precision=prec)
+            row["automatic"] = {"steps_per_launch": lat.steps_per_launch(),
+                                "form": "staged" if lat.two_step_form() == L.LBM_FORM_STAGED
+                                else "register"}
+            lat.close()
+            out["sizes"][f"{pname} {nx}x{ny}"] = row
+            print(f"sizes: {pname} {nx}x{ny} {row}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["sweep"], default="shear")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["sweep", "sizes"], default="shear",
+                    help="sizes: one step against two steps per launch, and the two forms of the "
+                         "two-step kernel, on cavities of 64 x 32 to 2048 x 4096 nodes")
     ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
     ap.add_argument("--steps-per-launch", type=int, choices=[0, 1, 2], default=0,
                     help="0 = the library's automatic choice")
@@ -598,6 +678,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "sizes":
+        bench_sizes()
         return
     print(f"bench: workload {args.workload} {args.precision}, {args.steps} steps", file=sys.stderr,
           flush=True)
@@ -649,12 +732,15 @@ def main():
         "nonfinite_at_step": main_r["nonfinite_at_step"],
         "copy_ceiling": copy,
     }
+    progress(f"headline run done: {out['value']} MLUPS")
     if full:
         if args.precision == "fp32dev":
             r64 = run_workload(args.workload, "fp64", L.LBM_RC, args)
+            progress(f"fp64 run done: {r64['mlups']:.1f} MLUPS")
             c64 = copy_gbs  # the copy ceiling does not depend on the value type
             out["fp64"] = dict(mlups=round(r64["mlups"], 1),
-                               roofline=roofline_of(r64, c64),
+                               roofline=roofline_of(r64, c64, traffic_of(
+                                   f"{args.workload}/fp64/{r64['steps_per_launch']}")),
                                one_step_per_launch=one_step_line(r64, c64),
                                target_mlups=round(TARGET_MLUPS["fp64"], 1),
                                mlups_vs_target=round(r64["mlups"] / TARGET_MLUPS["fp64"], 4))
@@ -662,6 +748,7 @@ def main():
                           one_step=False)
         out["rnr"] = dict(mlups=round(rn["mlups"], 1), kernel_us=round(1e3 * rn["kernel_ms"], 3),
                           steps_per_launch=rn["steps_per_launch"])
+        progress("rnr run done")
         if args.workload != "cavity":
             cav = run_workload("cavity", args.precision, L.LBM_RC, args)
             d = dict(workload="cavity 512x1024 r=0.5 Re=1000 lid=0.05 (both buffers fit the "
@@ -672,9 +759,12 @@ def main():
             if "two_step_ms" in cav:
                 d["two_step_kernel_us"] = round(1e3 * cav["two_step_ms"], 3)
             out["cavity_cache_resident"] = d
+            progress("cavity run done")
         if not args.no_steady:
             out["time_to_steady"], out["fp32_steady_error"] = cavity_steady()
+            progress("cavity to steady state done")
             out["time_to_steady"]["warm_start"] = warm_start_section()
+            progress("warm-start section done")
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(args.workload, L.LBM_RC, args.cpu_budget)
     out["kernel_sha"] = kernel_sha()

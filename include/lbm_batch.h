@@ -52,6 +52,11 @@ typedef struct {
                             start (the marching kernel while any case has a mask);
                             0 (default): the marching kernel until lbm_batch_autotune
                             chooses */
+    int steps_per_launch; /* 0 (default, automatic) or 2: while no case has a mask,
+                            advance pairs of steps with the two-steps-per-launch
+                            kernel (lbm_set_steps_per_launch) on 64 x 8 block tiles,
+                            the single steps with the tile kernel; 1: one step per
+                            launch.  Results are bit-identical either way. */
 } lbm_batch_opts;
 
 typedef struct lbm_batch lbm_batch;
@@ -96,7 +101,10 @@ int lbm_batch_set_active(lbm_batch *b, const int *active);
 
 /* Advances every active case by n >= 0 steps (enqueued; does not wait).
  * Whole graph replays cover runs of graph_steps steps, single launches the
- * rest.  Errors: LBM_E_INVAL (n < 0), LBM_E_DEVICE. */
+ * rest.  With two steps per launch (lbm_batch_steps_per_launch), pairs of
+ * steps run while more than two steps remain and the call ends with one or
+ * two single steps, so the residual of the last step is available.
+ * Errors: LBM_E_INVAL (n < 0), LBM_E_DEVICE. */
 int lbm_batch_step(lbm_batch *b, long n);
 
 /* Per-case steady-state residual of the last step of each case,
@@ -129,7 +137,9 @@ long lbm_batch_steps_done(const lbm_batch *b, int c);
  * persistent grid size of the marching kernel, and, when no case has a mask,
  * the one-node-per-thread tile kernel on 64 x 8 block tiles with three grid
  * sizes; it then reports 8 rows), trial_steps >= 1 launches each, and keeps
- * the fastest.  Setting a mask later returns the batch to the marching
+ * the fastest.  With two steps per launch in force it times only the
+ * two-step kernel's persistent grid (one block tile per workgroup, or 8, 4
+ * or 2 workgroups per CU) and reports 8 rows.  Setting a mask later returns the batch to the marching
  * kernel.  The trial launches recompute one step from the current state
  * without committing it, so no case advances; the residual of every case
  * needs a step afterwards.  rows_out / workgroups_out (may be NULL) receive
@@ -137,8 +147,14 @@ long lbm_batch_steps_done(const lbm_batch *b, int c);
 int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out, int *workgroups_out);
 
 /* 1 if the batch steps with the tile kernel (chosen by lbm_batch_autotune
- * when no case has a mask), 0 for the marching kernel; -1 for a NULL batch. */
+ * or taken with two steps per launch, when no case has a mask), 0 for the
+ * marching kernel; -1 for a NULL batch. */
 int lbm_batch_uses_tile_kernel(const lbm_batch *b);
+
+/* Steps per launch of the next long run: 2 while two steps per launch are
+ * allowed (lbm_batch_opts.steps_per_launch) and no case has a mask, else 1;
+ * LBM_E_INVAL for a NULL batch. */
+int lbm_batch_steps_per_launch(const lbm_batch *b);
 
 /* Current launch shape: rows per wavefront, persistent workgroups and the
  * number of tiles of the active cases.  Errors: LBM_E_INVAL. */

@@ -74,6 +74,11 @@ struct lbm_batch {
     int graph_steps;
     hipGraphExec_t graph;
     bool graph_ok;
+    // two steps per launch (lbm_batch_opts.steps_per_launch != 1, no mask)
+    int spl_opt;                // 0 automatic, 1, 2
+    int workgroups2;            // persistent grid of the two-step kernel
+    hipGraphExec_t graph2;      // captured runs of two-step launches
+    bool graph2_ok;
     char err[512];
 };
 
@@ -117,6 +122,21 @@ static bool any_mask(const lbm_batch *b) {
     return false;
 }
 
+// Two steps per launch apply while no case has a mask; they run on the block
+// tiles of the tile kernel, which then also takes the single steps.
+static bool two_step_on(const lbm_batch *b) { return b->spl_opt != 1 && !any_mask(b); }
+
+static bool tile_mode_wanted(const lbm_batch *b) {
+    return (b->tile_pref || b->spl_opt != 1) && !any_mask(b);
+}
+
+// two-step launches per captured graph: half the graph's steps, kept even so
+// that a replay leaves every case's current buffer where it was
+static int graph_pairs(const lbm_batch *b) {
+    const int p = (b->graph_steps / 2) & ~1;
+    return p < 2 ? 2 : p;
+}
+
 // block tiles of the batched tile kernel for one case
 static int block_tiles(const Geometry &G) {
     return G.nseg * ((G.ny + kBatchTileRows - 1) / kBatchTileRows);
@@ -126,10 +146,11 @@ static int block_tiles(const Geometry &G) {
 // mode, wavefront tiles of the march otherwise.  A mask on any case ends tile
 // mode (its generic loads would be slower than the march's near-solid tiles).
 static int upload_tiles(lbm_batch *b) {
-    const bool mode = b->tile_pref && !any_mask(b);
+    const bool mode = tile_mode_wanted(b);
     if (mode != b->tile_mode) {
         b->tile_mode = mode;
         b->graph_ok = false;  // the captured steps launch the other kernel
+        b->graph2_ok = false;
     }
     std::vector<BatchTile> t;
     t.reserve(b->tile_cap);
@@ -190,6 +211,7 @@ static int apply_rows(lbm_batch *b, int rows) {
     HIP_OK(b, hipMemcpyAsync(b->d_geoms, b->G.data(), b->n * sizeof(Geometry),
                              hipMemcpyHostToDevice, b->stream));
     b->graph_ok = false;
+    b->graph2_ok = false;
     int rc = upload_tiles(b);
     if (rc == LBM_OK) b->tiles_dirty = false;
     return rc;
@@ -203,6 +225,38 @@ static hipError_t launch(lbm_batch *b, int flip, int force_pull, int wgs) {
     return launch_batch_step(b->prec, b->coll, b->higher_unit, b->buf[0], b->buf[1], b->d_tiles,
                              b->d_ntiles, b->d_cases, b->d_geoms, b->d_Kd, b->d_Kf, flip,
                              force_pull, wgs, b->stream);
+}
+
+static hipError_t launch2(lbm_batch *b, int flip, int wgs) {
+    return launch_batch_tile2(b->prec, b->coll, b->higher_unit, b->buf[0], b->buf[1], b->d_tiles,
+                              b->d_ntiles, b->d_cases, b->d_geoms, b->d_Kd, b->d_Kf, flip, wgs,
+                              b->stream);
+}
+
+static int ensure_graph2(lbm_batch *b) {
+    if (b->graph2_ok) return LBM_OK;
+    if (b->graph2) {
+        HIP_OK(b, hipGraphExecDestroy(b->graph2));
+        b->graph2 = nullptr;
+    }
+    HIP_OK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < graph_pairs(b) && le == hipSuccess; ++i) le = launch2(b, i & 1, b->workgroups2);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(b, LBM_E_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&b->graph2, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        b->graph2 = nullptr;
+        return fail(b, LBM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ie));
+    }
+    b->graph2_ok = true;
+    return LBM_OK;
 }
 
 static int ensure_graph(lbm_batch *b) {
@@ -252,6 +306,7 @@ extern "C" int lbm_batch_destroy(lbm_batch *b) {
     if (!b) return LBM_OK;
     if (b->stream || b->own_stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph2) (void)hipGraphExecDestroy(b->graph2);
     void *ptrs[] = {b->buf[0], b->buf[1], b->d_cases, b->d_geoms, b->d_Kd, b->d_Kf, b->d_H,
                     b->d_tiles, b->d_ntiles, b->d_items, b->d_case_first, b->d_case_count,
                     b->d_partials, b->d_out, b->d_stage};
@@ -281,6 +336,8 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
     if (o.graph_steps == 0) o.graph_steps = 64;
     if (o.graph_steps < 2 || (o.graph_steps & 1))
         return fail(nullptr, LBM_E_INVAL, "graph_steps must be even and >= 2");
+    if (o.steps_per_launch < 0 || o.steps_per_launch > 2)
+        return fail(nullptr, LBM_E_INVAL, "steps_per_launch must be 0, 1 or 2");
     lbm_batch *b = new (std::nothrow) lbm_batch();
     if (!b) return fail(nullptr, LBM_E_NOMEM, "out of host memory");
     b->n = ncases;
@@ -288,6 +345,7 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
     b->prec = o.precision;
     b->coll = o.collision;
     b->graph_steps = o.graph_steps;
+    b->spl_opt = o.steps_per_launch;
     b->vbytes = f32_storage(o.precision) ? sizeof(float) : sizeof(double);
     snprintf(b->err, sizeof(b->err), "no error");
     try {
@@ -411,6 +469,10 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
         r = apply_rows(b, rows);
         if (r != LBM_OK) return r;
         b->workgroups = o.workgroups > 0 ? o.workgroups : auto_workgroups(b->ntiles);
+        // two-step grid: one block tile per workgroup (persistent beyond that)
+        int nbt = 0;
+        for (int c = 0; c < ncases; ++c) nbt += block_tiles(b->G[c]);
+        b->workgroups2 = o.workgroups > 0 ? o.workgroups : (nbt > 0 ? nbt : 1);
         for (int c = 0; c < ncases; ++c) {
             HIP_OK(b, launch_init_feq(b->prec, case_ptr(b, c, 0), nullptr, nullptr, nullptr,
                                       b->G[c], b->H[c], b->stream));
@@ -615,6 +677,18 @@ static void commit_steps(lbm_batch *b, long n) {
     }
 }
 
+// Host bookkeeping after `launches` two-step launches (2 launches steps) of
+// every active case: the other buffer then holds the state two steps back.
+static void commit_pairs(lbm_batch *b, long launches) {
+    if (launches <= 0) return;
+    for (int c = 0; c < b->n; ++c) {
+        if (!b->active[c]) continue;
+        b->form_prev[c] = kEmpty;
+        b->bc[c].cur ^= static_cast<int>(launches & 1);
+        b->steps[c] += 2 * launches;
+    }
+}
+
 extern "C" int lbm_batch_step(lbm_batch *b, long n) {
     if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
     if (n < 0) return fail(b, LBM_E_INVAL, "n must be >= 0");
@@ -634,6 +708,31 @@ extern "C" int lbm_batch_step(lbm_batch *b, long n) {
         int rc = upload_cases(b);
         if (rc != LBM_OK) return rc;
         --left;
+    }
+    if (two_step_on(b) && left >= 3) {
+        // pairs while more than two steps remain; the last launch advances
+        // one step, so the residual of the last step stays available
+        long pairs = (left - 1) / 2;
+        left -= 2 * pairs;
+        const int gp = graph_pairs(b);
+        if (pairs >= gp) {
+            int rc = ensure_graph2(b);
+            if (rc != LBM_OK) return rc;
+            const long reps = pairs / gp;
+            for (long i = 0; i < reps; ++i) HIP_OK(b, hipGraphLaunch(b->graph2, b->stream));
+            commit_pairs(b, reps * gp);  // an even number of launches
+            pairs -= reps * gp;
+        }
+        for (long i = 0; i < pairs; ++i) {
+            hipError_t e = launch2(b, static_cast<int>(i & 1), b->workgroups2);
+            if (e != hipSuccess)
+                return fail(b, LBM_E_DEVICE, "batch two-step launch failed: %s", hipGetErrorString(e));
+        }
+        commit_pairs(b, pairs);
+        if (pairs & 1) {
+            int rc = upload_cases(b);
+            if (rc != LBM_OK) return rc;
+        }
     }
     if (left >= b->graph_steps) {
         int rc = ensure_graph(b);
@@ -751,10 +850,54 @@ extern "C" long lbm_batch_steps_done(const lbm_batch *b, int c) {
     return b->steps[c];
 }
 
+// With two steps per launch the autotuner times the two-step kernel's
+// persistent grid: one block tile per workgroup, or 8, 4 or 2 workgroups per
+// CU.  Each trial recomputes the same pair of steps into the other buffer.
+static int autotune_two_step(lbm_batch *b, int trial_steps, int *rows_out, int *workgroups_out) {
+    int rc = ensure_tiles(b);
+    if (rc != LBM_OK) return rc;
+    const int nbt = b->ntiles;
+    hipEvent_t e0, e1;
+    HIP_OK(b, hipEventCreate(&e0));
+    HIP_OK(b, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_wgs = b->workgroups2;
+    for (int wgs : {nbt, 256 * 8, 256 * 4, 256 * 2}) {
+        if (nbt == 0) break;
+        if (wgs > nbt) wgs = nbt;
+        hipError_t e = launch2(b, 0, wgs);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int i = 0; i < trial_steps && e == hipSuccess; ++i) e = launch2(b, 0, wgs);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = fail(b, LBM_E_DEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            best_wgs = wgs;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) return rc;
+    b->workgroups2 = best_wgs;
+    b->graph2_ok = false;
+    // the other buffer of every case was overwritten by the trials
+    for (int c = 0; c < b->n; ++c) b->form_prev[c] = kEmpty;
+    if (rows_out) *rows_out = kBatchTileRows;
+    if (workgroups_out) *workgroups_out = best_wgs;
+    return LBM_OK;
+}
+
 extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
                                   int *workgroups_out) {
     if (!b) return fail(nullptr, LBM_E_INVAL, "batch is NULL");
     if (trial_steps < 1) return fail(b, LBM_E_INVAL, "trial_steps must be >= 1");
+    if (two_step_on(b)) return autotune_two_step(b, trial_steps, rows_out, workgroups_out);
     b->tile_pref = false;  // the march candidates first
     const int rows_c[] = {2, 4, 8, 16};
     const int wg_mult[] = {2, 4, 8, 0};  // x 256 CUs; 0: one tile per wavefront
@@ -832,6 +975,7 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
     if (rc != LBM_OK) return rc;
     b->workgroups = best_wgs;
     b->graph_ok = false;
+    b->graph2_ok = false;
     // the other buffer of every case was overwritten by the trials
     for (int c = 0; c < b->n; ++c) b->form_prev[c] = kEmpty;
     if (rows_out) *rows_out = best_rows;
@@ -842,10 +986,11 @@ extern "C" int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out,
 extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, int *workgroups,
                                       int *tiles) {
     if (!b) return LBM_E_INVAL;
-    // (tile mode reports its block-tile rows and block tiles)
-    const bool tile = b->tile_pref && !any_mask(b);
+    // (tile mode reports its block-tile rows and block tiles; with two steps
+    // per launch, the two-step kernel's grid)
+    const bool tile = tile_mode_wanted(b);
     if (rows_per_wave) *rows_per_wave = tile ? kBatchTileRows : b->rows;
-    if (workgroups) *workgroups = b->workgroups;
+    if (workgroups) *workgroups = two_step_on(b) ? b->workgroups2 : b->workgroups;
     if (tiles) {
         // count without touching the device when the list is stale
         int t = 0;
@@ -858,7 +1003,12 @@ extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, in
 
 extern "C" int lbm_batch_uses_tile_kernel(const lbm_batch *b) {
     if (!b) return -1;
-    return b->tile_pref && !any_mask(b) ? 1 : 0;
+    return tile_mode_wanted(b) ? 1 : 0;
+}
+
+extern "C" int lbm_batch_steps_per_launch(const lbm_batch *b) {
+    if (!b) return LBM_E_INVAL;
+    return two_step_on(b) ? 2 : 1;
 }
 
 extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {

@@ -196,6 +196,12 @@ hipError_t launch_batch_tile(int prec, int coll, bool higher_unit, void *buf0, v
                              const Geometry *geoms, const Consts<double> *Kd,
                              const Consts<float> *Kf, int flip, int force_pull, int workgroups,
                              hipStream_t st);
+// two steps per launch over the same block tiles (lbm_tile2.hip): every
+// active case must be in pull form and without a mask
+hipError_t launch_batch_tile2(int prec, int coll, bool higher_unit, void *buf0, void *buf1,
+                              const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                              const Geometry *geoms, const Consts<double> *Kd,
+                              const Consts<float> *Kf, int flip, int workgroups, hipStream_t st);
 // per-case residual sums of the batch: out[4 c + 0..3] as for launch_residual,
 // over the cases named by the reduction items (items of a case are contiguous)
 hipError_t launch_batch_residual(int prec, const void *buf0, const void *buf1,

@@ -461,18 +461,13 @@ tile2_staged_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geomet
         tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, false>(src, dst, G, K, x0, j0, pb, r1, r2);
 }
 
+// The register form on one 64 x TY tile at (x0, j0): interior tiles take
+// the buffer loads, edge tiles the per-lane x faces or the generic loader.
 template <typename S, typename R, bool DEV, int COLL, bool HU, int TY>
-__global__ void __launch_bounds__(kWave * TY)
-tile2_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
-                  const Consts<R> K, int ntx, int nty) {
+__device__ __forceinline__ void tile2_tile(const S *__restrict__ src, S *__restrict__ dst,
+                                           const Geometry &G, const Consts<R> &K, int x0, int j0,
+                                           S (*pb)[T2<TY>::PH][T2<TY>::PW], R *rr) {
     using C = T2<TY>;
-    __shared__ S pb[9][C::PH][C::PW];
-    __shared__ R rr[C::QH * C::QW];
-    int b = blockIdx.x;
-    const int nb = static_cast<int>(gridDim.x);
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
-    if (b >= ntx * nty) return;                             // padding workgroup (whole block)
-    const int x0 = (b % ntx) * kWave, j0 = (b / ntx) * TY;
     R(*r1)[C::QW] = reinterpret_cast<R(*)[C::QW]>(rr);
     R(*r2)[C::CW] = reinterpret_cast<R(*)[C::CW]>(rr);
     const bool walls = G.bc[kXmin] != kPeriodic || G.bc[kYmin] != kPeriodic;
@@ -490,6 +485,49 @@ tile2_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry
         tile2_body<S, R, DEV, COLL, HU, TY, 2, true>(src, dst, G, K, x0, j0, pb, r1, r2);
     else
         tile2_body<S, R, DEV, COLL, HU, TY, 2, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+}
+
+template <typename S, typename R, bool DEV, int COLL, bool HU, int TY>
+__global__ void __launch_bounds__(kWave * TY)
+tile2_step_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
+                  const Consts<R> K, int ntx, int nty) {
+    using C = T2<TY>;
+    __shared__ S pb[9][C::PH][C::PW];
+    __shared__ R rr[C::QH * C::QW];
+    int b = blockIdx.x;
+    const int nb = static_cast<int>(gridDim.x);
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
+    if (b >= ntx * nty) return;                             // padding workgroup (whole block)
+    tile2_tile<S, R, DEV, COLL, HU, TY>(src, dst, G, K, (b % ntx) * kWave, (b / ntx) * TY, pb, rr);
+}
+
+// Batched form: a persistent grid walks a list of 64 x kBatchTileRows block
+// tiles of all active cases (BatchTile {case, tile column, tile row}), every
+// case in pull form; case c reads buf[cur ^ flip] and writes the other
+// buffer.  The LDS tiles are reused, with a barrier between tiles.
+template <typename S, typename R, bool DEV, int COLL, bool HU>
+__global__ void __launch_bounds__(kWave * kBatchTileRows)
+batch_tile2_kernel(S *__restrict__ buf0, S *__restrict__ buf1, const BatchTile *__restrict__ tiles,
+                   const int *__restrict__ ntiles, const BatchCase *__restrict__ cases,
+                   const Geometry *__restrict__ geoms, const Consts<R> *__restrict__ Ks, int flip) {
+    constexpr int TY = kBatchTileRows;
+    using C = T2<TY>;
+    __shared__ S pb[9][C::PH][C::PW];
+    __shared__ R rr[C::QH * C::QW];
+    const int n = *ntiles;
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const BatchTile td = tiles[t];
+        const int c = __builtin_amdgcn_readfirstlane(td.c);
+        const int tcol = __builtin_amdgcn_readfirstlane(td.seg);
+        const int trow = __builtin_amdgcn_readfirstlane(td.chunk);
+        const int cur = __builtin_amdgcn_readfirstlane(cases[c].cur) ^ flip;
+        const long long off = cases[c].off;
+        const S *src = (cur ? buf1 : buf0) + off;
+        S *dst = (cur ? buf0 : buf1) + off;
+        tile2_tile<S, R, DEV, COLL, HU, TY>(src, dst, geoms[c], Ks[c], tcol * kWave, trow * TY, pb,
+                                            rr);
+        __syncthreads();  // the next tile reuses the LDS tiles
+    }
 }
 
 // Rows of the register form's output tile.  Measured on the 2048 x 8192
@@ -585,6 +623,39 @@ hipError_t launch_step2(int prec, int coll, bool hu, int form, const void *src, 
     case kFP32Dev: return tile2_dispatch<float, float, true>(coll, hu, f, src, dst, G, Kf, st);
     case kFP64Dev: return tile2_dispatch<double, double, true>(coll, hu, f, src, dst, G, Kd, st);
     case kFP32DevF64: return tile2_dispatch<float, double, true>(coll, hu, f, src, dst, G, Kd, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename S, typename R, bool DEV>
+static hipError_t batch_tile2_dispatch(int coll, bool hu, void *b0, void *b1,
+                                       const BatchTile *tiles, const int *ntiles,
+                                       const BatchCase *cases, const Geometry *geoms,
+                                       const Consts<R> *K, int flip, int wgs, hipStream_t st) {
+    static_assert(kBatchTileRows == tile2_rows<R>(), "block tiles of the register form");
+    const dim3 grid(wgs), block(kWave * kBatchTileRows);
+#define LBM_BT2(CO, H)                                                                            \
+    hipLaunchKernelGGL((batch_tile2_kernel<S, R, DEV, CO, H>), grid, block, 0, st,                 \
+                       static_cast<S *>(b0), static_cast<S *>(b1), tiles, ntiles, cases, geoms,   \
+                       K, flip)
+    if (coll == kRC) {
+        if (hu) LBM_BT2(kRC, true); else LBM_BT2(kRC, false);
+    } else {
+        if (hu) LBM_BT2(kRNR, true); else LBM_BT2(kRNR, false);
+    }
+#undef LBM_BT2
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile2(int prec, int coll, bool hu, void *b0, void *b1,
+                              const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                              const Geometry *geoms, const Consts<double> *Kd,
+                              const Consts<float> *Kf, int flip, int wgs, hipStream_t st) {
+    switch (prec) {
+    case kFP64: return batch_tile2_dispatch<double, double, false>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, wgs, st);
+    case kFP32Dev: return batch_tile2_dispatch<float, float, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kf, flip, wgs, st);
+    case kFP64Dev: return batch_tile2_dispatch<double, double, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, wgs, st);
+    case kFP32DevF64: return batch_tile2_dispatch<float, double, true>(coll, hu, b0, b1, tiles, ntiles, cases, geoms, Kd, flip, wgs, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -39,7 +39,7 @@ BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fi
                  "lbm_batch_set_active", "lbm_batch_step", "lbm_batch_residuals",
                  "lbm_batch_run_to_steady", "lbm_batch_moments", "lbm_batch_get_populations",
                  "lbm_batch_set_populations", "lbm_batch_steps_done", "lbm_batch_autotune",
-                 "lbm_batch_uses_tile_kernel",
+                 "lbm_batch_uses_tile_kernel", "lbm_batch_steps_per_launch",
                  "lbm_batch_launch_shape", "lbm_batch_last_error", "lbm_batch_destroy")
 
 
@@ -92,6 +92,7 @@ class lbm_batch_opts(ctypes.Structure):
         ("graph_steps", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("tile_kernel", ctypes.c_int),
+        ("steps_per_launch", ctypes.c_int),
     ]
 
 
@@ -198,6 +199,8 @@ def load():
     L.lbm_batch_launch_shape.argtypes = [_B, _I, _I, _I]
     L.lbm_batch_uses_tile_kernel.argtypes = [_B]
     L.lbm_batch_uses_tile_kernel.restype = ctypes.c_int
+    L.lbm_batch_steps_per_launch.argtypes = [_B]
+    L.lbm_batch_steps_per_launch.restype = ctypes.c_int
     L.lbm_batch_last_error.argtypes = [_B]
     L.lbm_batch_last_error.restype = ctypes.c_char_p
     L.lbm_batch_destroy.argtypes = [_B]
@@ -622,6 +625,13 @@ def lbm_batch_uses_tile_kernel(b) -> bool:
     return load().lbm_batch_uses_tile_kernel(b) == 1
 
 
+def lbm_batch_steps_per_launch(b) -> int:
+    k = load().lbm_batch_steps_per_launch(b)
+    if k < 0:
+        raise LbmError(k, "NULL batch")
+    return k
+
+
 def lbm_batch_autotune(b, trial_steps=5):
     r, w = ctypes.c_int(), ctypes.c_int()
     _bcheck(load().lbm_batch_autotune(b, int(trial_steps), ctypes.byref(r), ctypes.byref(w)), b)
@@ -647,10 +657,12 @@ class Batch:
     """Owns one lbm_batch: cases is a list of lbm_case (see make_case)."""
 
     def __init__(self, cases, collision=LBM_RC, precision=LBM_FP64, corrections=True,
-                 rows_per_wave=0, workgroups=0, graph_steps=0, stream=None, tile_kernel=False):
+                 rows_per_wave=0, workgroups=0, graph_steps=0, stream=None, tile_kernel=False,
+                 steps_per_launch=0):
         """stream: a hipStream_t handle (e.g. torch.cuda.Stream().cuda_stream)
         or None for a stream the batch creates; tile_kernel: step with the
-        tile kernel from the start (else the autotuner chooses)."""
+        tile kernel from the start (else the autotuner chooses);
+        steps_per_launch: 0 automatic (two while no case has a mask), 1, 2."""
         self.shapes = [(c.nx, c.ny) for c in cases]
         self.n = len(cases)
         o = lbm_batch_default_opts()
@@ -659,6 +671,7 @@ class Batch:
         o.rows_per_wave, o.workgroups, o.graph_steps = int(rows_per_wave), int(workgroups), int(graph_steps)
         o.stream = stream
         o.tile_kernel = 1 if tile_kernel else 0
+        o.steps_per_launch = int(steps_per_launch)
         self.b = lbm_batch_create(cases, o)
 
     def set_fields(self, c, rho=None, ux=None, uy=None):
@@ -702,6 +715,9 @@ class Batch:
 
     def uses_tile_kernel(self):
         return lbm_batch_uses_tile_kernel(self.b)
+
+    def steps_per_launch(self):
+        return lbm_batch_steps_per_launch(self.b)
 
     def launch_shape(self):
         return lbm_batch_launch_shape(self.b)

@@ -314,3 +314,62 @@ def test_tile_kernel_returns_when_the_masks_are_removed():
     assert np.array_equal(b.get_populations(1), lat.get_populations())
     lat.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+@pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
+@pytest.mark.parametrize("general", [False, True])
+def test_two_steps_per_launch_batch_is_bitwise_the_one_step_batch(prec, coll, general):
+    """Pairs of steps per launch (graph replays of pairs, single pair
+    launches and the closing single steps), through a deactivated case and a
+    case reset mid-run, against the same batch at one step per launch:
+    populations, step counts and residuals bit for bit.  A mask turns the
+    pairs off."""
+    announce("batch two-step", prec, coll, general)
+    rates = GENERAL if general else None
+    bs = [L.Batch(cases_of(SPECS, rates), collision=coll, precision=prec, graph_steps=4,
+                  steps_per_launch=k) for k in (1, 0)]
+    assert bs[0].steps_per_launch() == 1 and bs[1].steps_per_launch() == 2
+    for b in bs:
+        for c, spec in enumerate(SPECS):
+            b.set_fields(c, *I.random_fields(300 + c, spec[0], spec[1]))
+        b.step(14)  # the in-place step, three graph replays of two pairs, one step
+        b.set_active([1, 1, 0, 1, 1, 1])
+        b.step(6)   # one replay, two single steps
+        b.set_fields(4)
+        b.step(9)   # the in-place step, one replay, one pair, two single steps
+    for c in range(len(SPECS)):
+        assert bs[0].steps_done(c) == bs[1].steps_done(c)
+        assert np.array_equal(bs[0].get_populations(c), bs[1].get_populations(c)), c
+    assert np.array_equal(bs[0].residuals(), bs[1].residuals())
+    nx, ny = bs[1].shapes[2]
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[ny // 2:ny // 2 + 2, 5:9] = 1
+    bs[1].set_mask(2, mask)
+    assert bs[1].steps_per_launch() == 1
+    bs[1].set_mask(2, None)
+    assert bs[1].steps_per_launch() == 2
+    for b in bs:
+        b.close()
+
+
+def test_two_step_batch_autotune_and_run_to_steady():
+    """The autotuner's two-step trials leave the state as it was; a run to
+    steady state with pairs of steps stops at the same step, with the same
+    residuals, as at one step per launch."""
+    announce("batch two-step autotune and steady")
+    bs = [L.Batch(cases_of(SPECS[:3]), graph_steps=8, steps_per_launch=k) for k in (1, 0)]
+    for b in bs:
+        b.step(5)
+    before = [bs[1].get_populations(c) for c in range(3)]
+    rows, wgs = bs[1].autotune(2)
+    assert rows == 8 and wgs >= 1 and bs[1].launch_shape()[:2] == (8, wgs)
+    for c in range(3):
+        assert np.array_equal(bs[1].get_populations(c), before[c])
+    steps = [b.run_to_steady(1e-6, 50, 3000) for b in bs]
+    assert np.array_equal(steps[0], steps[1])
+    for c in range(3):
+        assert np.array_equal(bs[0].get_populations(c), bs[1].get_populations(c)), c
+    assert np.array_equal(bs[0].residuals(), bs[1].residuals())
+    for b in bs:
+        b.close()
