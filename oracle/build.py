@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 def build(verbose: bool = False) -> str:
     # -ffp-contract=off: no fused multiply-add, so every product is rounded
-    # exactly as written in the matrix form (vectorisation without fast-math
+    # exactly as written (vectorisation without fast-math
     # does not reorder sums, so the results do not depend on -O or -march).
     # x86-64-v3 (AVX2) rather than -march=native: the library is built on one
     # machine and run on another, whose CPU may lack this one's extensions.

@@ -7,11 +7,19 @@
  * TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the CPU
  * baseline of the benchmark.  The product path never calls it.
  *
- * Deliberately written in the paper's matrix-vector form (the paper itself
- * recommends component form for speed, Sec. 3; this file does the opposite
- * so that it shares no structure with the GPU path).  Each step follows the
- * order of Sec. 3 / Sec. 4: moments, relaxation, back-transform, stream,
- * update of the hydrodynamic fields.
+ * Written from the definitions, in the opposite form to the GPU path's
+ * component form (the paper recommends the component form for speed,
+ * Sec. 3): the raw and central moments of a node are direct sums of the
+ * basis monomials of Eq. 3 over its populations, evaluated at e_i (raw) or
+ * e_i - u (central, Eq. 43); after relaxation the post-collision populations
+ * are the solution of the 9 x 9 linear system "these populations have these
+ * moments", solved by Gaussian elimination.  The equilibrium populations are
+ * found the same way from the central equilibria of Eq. 49.  The matrices
+ * the paper prints for the transforms (T^{-1}, App. A; F(u), Eq. 53) are
+ * kept only as functions the tests pin against the printed values; the
+ * scheme does not use them.  Each step follows the order of Sec. 3 / Sec. 4:
+ * moments, relaxation, back to populations, stream, update of the
+ * hydrodynamic fields.
  *
  * Readings taken where the printed text is garbled or silent (each one is
  * listed with its justification in the design notes of the repository):
@@ -44,16 +52,6 @@ static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 /* e_ibar = -e_i */
 static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
-static void matvec9(const double *M, const double *v, double *out)
-{
-    for (int r = 0; r < 9; ++r) {
-        double s = 0.0;
-        for (int c = 0; c < 9; ++c)
-            s += M[r * 9 + c] * v[c];
-        out[r] = s;
-    }
-}
-
 /* Eq. 3: T = [|1>, |ex>, |ey>, |ex^2+ey^2>, |ex^2-ey^2>, |ex ey>, |ex^2 ey>,
  * |ex ey^2>, |ex^2 ey^2>] as rows, evaluated on the velocity set of Eq. 2. */
 void orc_T(double a, double *T)
@@ -72,8 +70,109 @@ void orc_T(double a, double *T)
     }
 }
 
+/* The nine monomials of the moment basis of Eq. 3 at a velocity (vx, vy):
+ * 1, vx, vy, vx^2 + vy^2, vx^2 - vy^2, vx vy, vx^2 vy, vx vy^2, vx^2 vy^2. */
+static void basis9(double vx, double vy, double *phi)
+{
+    phi[0] = 1.0;
+    phi[1] = vx;
+    phi[2] = vy;
+    phi[3] = vx * vx + vy * vy;
+    phi[4] = vx * vx - vy * vy;
+    phi[5] = vx * vy;
+    phi[6] = vx * vx * vy;
+    phi[7] = vx * vy * vy;
+    phi[8] = vx * vx * vy * vy;
+}
+
+/* Moments of a node's populations about the velocity (ux, uy):
+ * m_j = sum_i f_i phi_j(e_i - u).  With u = 0 these are the raw moments of
+ * Eq. 3; with the node's own velocity, the central moments of Eq. 43. */
+static void moments_about(double a, double ux, double uy, const double *f9, double *m)
+{
+    for (int j = 0; j < 9; ++j)
+        m[j] = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        double phi[9];
+        basis9(CX[i] - ux, a * CY[i] - uy, phi);
+        for (int j = 0; j < 9; ++j)
+            m[j] += f9[i] * phi[j];
+    }
+}
+
+/* The populations f whose moments about (ux, uy) are m: the 9 x 9 system
+ * sum_i phi_j(e_i - u) f_i = m_j, solved by LU factorisation with partial
+ * pivoting and one step of iterative refinement (the residual of the first
+ * solution, solved with the same factors and added), so that each solution
+ * is accurate to about one rounding of its components. */
+static void populations_with_moments(double a, double ux, double uy, const double *m,
+                                     double *f9)
+{
+    double A[9][9], LU[9][9], x[9] = {0}, r[9] = {0};
+    int perm[9];
+    for (int i = 0; i < 9; ++i) {
+        double phi[9];
+        basis9(CX[i] - ux, a * CY[i] - uy, phi);
+        for (int j = 0; j < 9; ++j)
+            A[j][i] = LU[j][i] = phi[j];
+    }
+    for (int j = 0; j < 9; ++j)
+        perm[j] = j;
+    for (int c = 0; c < 9; ++c) {
+        int piv = c;
+        for (int q = c + 1; q < 9; ++q)
+            if (fabs(LU[q][c]) > fabs(LU[piv][c]))
+                piv = q;
+        if (piv != c) {
+            for (int q = 0; q < 9; ++q) {
+                const double t = LU[c][q];
+                LU[c][q] = LU[piv][q];
+                LU[piv][q] = t;
+            }
+            const int t = perm[c];
+            perm[c] = perm[piv];
+            perm[piv] = t;
+        }
+        for (int q = c + 1; q < 9; ++q) {
+            LU[q][c] /= LU[c][c];
+            for (int w = c + 1; w < 9; ++w)
+                LU[q][w] -= LU[q][c] * LU[c][w];
+        }
+    }
+    /* solve L U x = P b, for b = m and then for the residual */
+    for (int pass = 0; pass < 2; ++pass) {
+        double y[9];
+        for (int j = 0; j < 9; ++j) {
+            double v = pass == 0 ? m[perm[j]] : r[perm[j]];
+            for (int q = 0; q < j; ++q)
+                v -= LU[j][q] * y[q];
+            y[j] = v;
+        }
+        for (int j = 8; j >= 0; --j) {
+            double v = y[j];
+            for (int q = j + 1; q < 9; ++q)
+                v -= LU[j][q] * y[q];
+            y[j] = v / LU[j][j];
+        }
+        if (pass == 0) {
+            for (int j = 0; j < 9; ++j)
+                x[j] = y[j];
+            for (int j = 0; j < 9; ++j) {
+                double v = m[j];
+                for (int i = 0; i < 9; ++i)
+                    v -= A[j][i] * x[i];
+                r[j] = v;
+            }
+        } else {
+            for (int j = 0; j < 9; ++j)
+                f9[j] = x[j] + y[j];
+        }
+    }
+}
+
 /* App. A, Eq. (Tinverse), with r1, r2 as defined there and the sign of
- * row 0 / column 8 read as +1/a^2. */
+ * row 0 / column 8 read as +1/a^2.  Not used by the scheme (which solves for
+ * the populations); kept for the tests that pin the printed matrix. */
 void orc_Tinv(double a, double *Ti)
 {
     const double a2 = a * a;
@@ -95,7 +194,9 @@ void orc_Tinv(double a, double *Ti)
 }
 
 /* App. B, Eq. 53: frame transformation F(u) from raw to central moments.
- * Its inverse is F(-u) (Eq. 55). */
+ * Its inverse is F(-u) (Eq. 55).  Not used by the scheme (which sums the
+ * central moments directly); kept for the tests that pin the printed
+ * matrix. */
 void orc_F(double ux, double uy, double *F)
 {
     const double ux2 = ux * ux, uy2 = uy * uy;
@@ -129,19 +230,14 @@ void orc_macro(const orc_params *p, const double *f9, double *rho, double *ux, d
     *uy = (jy + 0.5 * p->force[1]) / r;
 }
 
-/* Equilibrium populations: raw equilibria are the binomial transform of the
- * central equilibria (Sec. 2.1, text before Eq. 12), so
- * feq = T^{-1} F(-u) (rho, 0, 0, 2 rho cs^2, 0, 0, 0, 0, rho cs^4)
- * -- Eq. 49 without the corrections. */
+/* Equilibrium populations: the populations whose central moments are the
+ * central equilibria of Eq. 49 without the corrections,
+ * (rho, 0, 0, 2 rho cs^2, 0, 0, 0, 0, rho cs^4) about the velocity u. */
 void orc_feq(const orc_params *p, double rho, double ux, double uy, double *feq9)
 {
     const double s = p->cs2;
     const double mceq[9] = {rho, 0, 0, 2 * rho * s, 0, 0, 0, 0, rho * s * s};
-    double Finv[81], Ti[81], m[9];
-    orc_F(-ux, -uy, Finv);
-    orc_Tinv(p->a, Ti);
-    matvec9(Finv, mceq, m);
-    matvec9(Ti, m, feq9);
+    populations_with_moments(p->a, ux, uy, mceq, feq9);
 }
 
 /* Eq. 12 (square-lattice raw equilibria), m_8 coefficient read as 1. */
@@ -222,9 +318,8 @@ static void corrections_from(const orc_params *p, double rho, double ux, double 
 void orc_strain_rate(const orc_params *p, const double *f9, double drho_dx, double drho_dy,
                      double *dux_dx, double *duy_dy)
 {
-    double T[81], m[9], rho, ux, uy;
-    orc_T(p->a, T);
-    matvec9(T, f9, m);
+    double m[9], rho, ux, uy;
+    moments_about(p->a, 0.0, 0.0, f9, m);
     orc_macro(p, f9, &rho, &ux, &uy);
     strain_rate_from(p, m, rho, ux, uy, drho_dx, drho_dy, dux_dx, duy_dy);
 }
@@ -232,66 +327,60 @@ void orc_strain_rate(const orc_params *p, const double *f9, double drho_dx, doub
 void orc_corrections(const orc_params *p, const double *f9, double drho_dx, double drho_dy,
                      double *delta3, double *delta4)
 {
-    double T[81], m[9], rho, ux, uy, X, Y;
-    orc_T(p->a, T);
-    matvec9(T, f9, m);
+    double m[9], rho, ux, uy, X, Y;
+    moments_about(p->a, 0.0, 0.0, f9, m);
     orc_macro(p, f9, &rho, &ux, &uy);
     strain_rate_from(p, m, rho, ux, uy, drho_dx, drho_dy, &X, &Y);
     corrections_from(p, rho, ux, uy, drho_dx, drho_dy, X, Y, delta3, delta4);
 }
 
-/* One node's collision.  T and Ti are passed in so the field loops build
- * them once. */
-static void collide_with(const orc_params *p, const double *T, const double *Ti,
-                         const double *f9, double gx, double gy, double *out9)
+/* One node's collision. */
+static void collide_with(const orc_params *p, const double *f9, double gx, double gy,
+                         double *out9)
 {
     const double s = p->cs2;
     const double *w = p->omega;
     const double Fx = p->force[0], Fy = p->force[1];
     double rho, ux, uy, X, Y, d3, d4;
-    double m[9], mt[9];
+    double m[9];
 
-    /* pre-collision raw moments m = T f */
-    matvec9(T, f9, m);
+    /* hydrodynamic fields and the raw moments (Eq. 3) */
     orc_macro(p, f9, &rho, &ux, &uy);
+    moments_about(p->a, 0.0, 0.0, f9, m);
     /* local strain rate (Eq. 37-38) and corrections (Eq. 23-27) */
     strain_rate_from(p, m, rho, ux, uy, gx, gy, &X, &Y);
     corrections_from(p, rho, ux, uy, gx, gy, X, Y, &d3, &d4);
 
     if (p->collision == ORC_RC) {
-        /* Sec. 4: m^c = F m; relax toward Eq. 49 with central sources
-         * (0, Fx, Fy, 0, ...); back with F^{-1} = F(-u). */
-        double F[81], Finv[81], mc[9], mct[9];
+        /* Sec. 4: central moments (Eq. 43) relaxed toward Eq. 49 with the
+         * central sources (0, Fx, Fy, 0, ...); the post-collision populations
+         * are those with the relaxed central moments. */
+        double mc[9], mct[9];
         const double mceq[9] = {rho, 0, 0, 2 * rho * s + d3, d4, 0.0, 0, 0, rho * s * s};
         const double phic[9] = {0, Fx, Fy, 0, 0, 0, 0, 0, 0};
-        orc_F(ux, uy, F);
-        orc_F(-ux, -uy, Finv);
-        matvec9(F, m, mc);
+        moments_about(p->a, ux, uy, f9, mc);
         for (int j = 0; j < 9; ++j)
             mct[j] = mc[j] + w[j] * (mceq[j] - mc[j]) + (1 - w[j] / 2) * phic[j];
-        matvec9(Finv, mct, mt);
+        populations_with_moments(p->a, ux, uy, mct, out9);
     } else {
-        /* Sec. 3: relax raw moments toward m^{eq,r} + corrections (Eq. 10)
-         * with the sources of Eq. 13. */
-        double meq[9], phi[9];
+        /* Sec. 3: raw moments relaxed toward m^{eq,r} + corrections (Eq. 10,
+         * Eq. 12) with the sources of Eq. 13; the post-collision populations
+         * are those with the relaxed raw moments. */
+        double meq[9], phi[9], mt[9];
         raw_equilibria(rho, ux, uy, s, meq);
         meq[3] += d3;
         meq[4] += d4;
         raw_sources(Fx, Fy, ux, uy, phi);
         for (int j = 0; j < 9; ++j)
             mt[j] = m[j] + w[j] * (meq[j] - m[j]) + (1 - w[j] / 2) * phi[j];
+        populations_with_moments(p->a, 0.0, 0.0, mt, out9);
     }
-    /* post-collision populations f~ = T^{-1} m~ */
-    matvec9(Ti, mt, out9);
 }
 
 void orc_collide_node(const orc_params *p, const double *f9, double drho_dx, double drho_dy,
                       double *out9)
 {
-    double T[81], Ti[81];
-    orc_T(p->a, T);
-    orc_Tinv(p->a, Ti);
-    collide_with(p, T, Ti, f9, drho_dx, drho_dy, out9);
+    collide_with(p, f9, drho_dx, drho_dy, out9);
 }
 
 /* ---------------------------------------------------------------- fields */
@@ -310,10 +399,15 @@ static void gather9(const orc_params *p, const double *f, int i, int j, double *
         f9[k] = f[FIDX(p, k, j, i)];
 }
 
+/* Lattices below this many nodes run on one thread: for them the cost of
+ * starting a parallel region every step exceeds the work.  Every node is
+ * computed independently, so the results do not depend on the threads. */
+static int threaded(const orc_params *p) { return (long)p->nx * p->ny >= 8192; }
+
 void orc_init(const orc_params *p, const double *rho, const double *ux, const double *uy,
               double *f)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i) {
             double feq[9];
@@ -329,7 +423,7 @@ void orc_init(const orc_params *p, const double *rho, const double *ux, const do
 
 void orc_density(const orc_params *p, const double *f, double *rho)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i) {
             double r = 0.0;
@@ -372,7 +466,7 @@ static int nb_y(const orc_params *p, int i, int j, int d)
 void orc_density_gradient(const orc_params *p, const double *rho, double *gx, double *gy)
 {
     const int nx = p->nx, ny = p->ny;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             gx[IDX(p, j, i)] =
@@ -390,17 +484,14 @@ void orc_collide(const orc_params *p, const double *f, double *ft)
     double *rho = malloc(n * sizeof(double));
     double *gx = malloc(n * sizeof(double));
     double *gy = malloc(n * sizeof(double));
-    double T[81], Ti[81];
-    orc_T(p->a, T);
-    orc_Tinv(p->a, Ti);
     orc_density(p, f, rho);
     orc_density_gradient(p, rho, gx, gy);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i) {
             double f9[9], o9[9];
             gather9(p, f, i, j, f9);
-            collide_with(p, T, Ti, f9, gx[IDX(p, j, i)], gy[IDX(p, j, i)], o9);
+            collide_with(p, f9, gx[IDX(p, j, i)], gy[IDX(p, j, i)], o9);
             for (int k = 0; k < 9; ++k)
                 ft[FIDX(p, k, j, i)] = o9[k];
         }
@@ -438,8 +529,9 @@ static int link_source(const orc_params *p, int i, int j, int k, int *si_out, in
     return -1;
 }
 
-/* (feq_ibar - feq_i)(rho_w, u_w) of every face; rho_w = rho0, u_w = 0 for a
- * stationary wall (then the difference vanishes). */
+/* (feq_ibar - feq_i)(rho_w, u_w) of every face; rho_w = rho0.  For a wall
+ * at rest the difference is zero (the equilibrium at u = 0 is symmetric
+ * under e -> -e) and is set so, exactly. */
 static void wall_terms(const orc_params *p, double dwall[5][9])
 {
     for (int face = 0; face < 4; ++face) {
@@ -447,7 +539,7 @@ static void wall_terms(const orc_params *p, double dwall[5][9])
         const int mv = p->bc_type[face] == ORC_MOVING_WALL;
         orc_feq(p, p->rho0, mv ? p->u_wall[face][0] : 0.0, mv ? p->u_wall[face][1] : 0.0, feq);
         for (int k = 0; k < 9; ++k)
-            dwall[face][k] = feq[OPP[k]] - feq[k];
+            dwall[face][k] = mv ? feq[OPP[k]] - feq[k] : 0.0;
     }
     for (int k = 0; k < 9; ++k)
         dwall[ORC_OBSTACLE][k] = 0.0;  /* obstacles are at rest */
@@ -460,7 +552,7 @@ void orc_stream(const orc_params *p, const double *ft, double *f)
     double dwall[5][9], rest[9];
     wall_terms(p, dwall);
     orc_feq(p, p->rho0, 0.0, 0.0, rest);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i)
             for (int k = 0; k < 9; ++k) {
@@ -491,9 +583,7 @@ static double node_density(const orc_params *p, const double *f, int i, int j)
  * central-difference density gradient) and streamed as in orc_stream. */
 void orc_step_node(const orc_params *p, const double *f, int i, int j, double *out9)
 {
-    double T[81], Ti[81], dwall[5][9];
-    orc_T(p->a, T);
-    orc_Tinv(p->a, Ti);
+    double dwall[5][9];
     wall_terms(p, dwall);
     if (is_solid(p, i, j)) {
         orc_feq(p, p->rho0, 0.0, 0.0, out9);
@@ -509,7 +599,7 @@ void orc_step_node(const orc_params *p, const double *f, int i, int j, double *o
                            node_density(p, f, nb_x(p, si, sj, -1), sj)) / 2.0;
         const double gy = (node_density(p, f, si, nb_y(p, si, sj, 1)) -
                            node_density(p, f, si, nb_y(p, si, sj, -1))) / (2.0 * p->a);
-        collide_with(p, T, Ti, f9, gx, gy, o9);
+        collide_with(p, f9, gx, gy, o9);
         out9[k] = o9[comp] - (face >= 0 ? dwall[face][k] : 0.0);
     }
 }
@@ -541,14 +631,12 @@ void orc_stress(const orc_params *p, const double *f, double *sxx, double *syy, 
     double *rho = malloc(n * sizeof(double));
     double *gx = malloc(n * sizeof(double));
     double *gy = malloc(n * sizeof(double));
-    double T[81];
-    orc_T(p->a, T);
     orc_density(p, f, rho);
     orc_density_gradient(p, rho, gx, gy);
     const double s = p->cs2;
     const double nu4 = s * (1.0 / p->omega[4] - 0.5), nu5 = s * (1.0 / p->omega[5] - 0.5);
     const double zeta = s * (1.0 / p->omega[3] - 0.5);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i) {
             const size_t q = IDX(p, j, i);
@@ -558,7 +646,7 @@ void orc_stress(const orc_params *p, const double *f, double *sxx, double *syy, 
             }
             double f9[9], m[9], r, ux, uy, X, Y;
             gather9(p, f, i, j, f9);
-            matvec9(T, f9, m);
+            moments_about(p->a, 0.0, 0.0, f9, m);
             orc_macro(p, f9, &r, &ux, &uy);
             strain_rate_from(p, m, r, ux, uy, gx[q], gy[q], &X, &Y);
             const double S = (m[5] - r * ux * uy) / (-r * s / p->omega[5]);
@@ -574,7 +662,7 @@ void orc_stress(const orc_params *p, const double *f, double *sxx, double *syy, 
 
 void orc_moments(const orc_params *p, const double *f, double *rho, double *ux, double *uy)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (threaded(p))
     for (int j = 0; j < p->ny; ++j)
         for (int i = 0; i < p->nx; ++i) {
             double f9[9], r, vx, vy;

@@ -8,13 +8,18 @@
  * product path never links, loads or calls it.  It shares no code, header,
  * table or constant generator with the HIP library.
  *
- * Everything is FP64 and written in the paper's literal matrix form:
- *   T (Eq. 3-4), T^{-1} (App. A), F(u) and F(-u) (App. B, Eq. 53/55),
- *   raw equilibria (Eq. 12), raw sources (Eq. 13), corrections (Eq. 23-27),
- *   local strain rate (Eq. 37-38, coefficients Eq. 40),
- *   RNR collision (Sec. 3), RC collision (Sec. 4, RC-LBE),
- *   perfect-shift streaming, half-way bounce-back and the moving-wall
- *   correction (Sec. 5.2, Eq. 57-59).
+ * Everything is FP64 and written from the definitions: raw moments as sums
+ * of the basis monomials of Eq. 3 over the populations, central moments as
+ * the same sums about the node's velocity (Eq. 43), and the way back to
+ * populations as the solution of the 9 x 9 linear system "these
+ * populations have these moments" (Gaussian elimination); raw equilibria
+ * (Eq. 12), raw sources (Eq. 13), central equilibria (Eq. 49), corrections
+ * (Eq. 23-27), local strain rate (Eq. 37-38, coefficients Eq. 40), RNR
+ * collision (Sec. 3), RC collision (Sec. 4), perfect-shift streaming,
+ * half-way bounce-back and the moving-wall correction (Sec. 5.2,
+ * Eq. 57-59).  The matrices the paper prints (T of Eq. 4, T^{-1} of App. A,
+ * F(u) of Eq. 53) are exported for the tests that pin them; the scheme
+ * does not use T^{-1} or F.
  *
  * Layout of every field: [9][ny][nx] for populations, [ny][nx] for scalar
  * fields, x fastest.  Node (i, j) sits at x = i (+1/2), y = (j + 1/2) * a.
