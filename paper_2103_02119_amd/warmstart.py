@@ -483,9 +483,34 @@ def predict_fields(net, scales, masks, params):
 
 
 SETTLE_STEPS = 50   # steps before the smoothing step of a start from fields
+CONSISTENT_STEPS = 100  # steps of the consistent start (velocity held at the prediction)
 
 
 MODES = ("cold", "cold+smooth", "warm", "warm+smooth")
+# further starts that warm_vs_cold knows (not run by default)
+EXTRA_MODES = ("consistent", "consistent+smooth")
+
+
+def consistent_start(b, pred, masks, steps=CONSISTENT_STEPS):
+    """A start consistent with the predicted velocity in the manner of Mei,
+    Luo, Lallemand and d'Humieres (Comput. Fluids 2006): from the predicted
+    fields at equilibrium, take `steps` steps, after each one moving every
+    fluid node's equilibrium part back to the predicted velocity at the
+    node's current density, f <- f + feq(rho, u_pred) - feq(rho, u); the
+    density and the non-equilibrium parts develop, the velocity stays.
+    Equilibria come from the library (lbm_batch_set_fields), so this runs
+    through the public API only."""
+    for _ in range(steps):
+        b.step(1)
+        for c, (_, ux_p, uy_p) in enumerate(pred):
+            rho, ux, uy = b.moments(c)
+            f = b.get_populations(c)
+            b.set_fields(c, rho, ux, uy)
+            f_now = b.get_populations(c)
+            b.set_fields(c, rho, ux_p, uy_p)
+            f_pred = b.get_populations(c)
+            fluid = (masks[c] == 0)[None]
+            b.set_populations(c, np.where(fluid, f + (f_pred - f_now), f))
 
 
 def _compare(res, ref, mode):
@@ -507,7 +532,10 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
       cold        from rest,
       cold+smooth from rest, with one smoothing step after SETTLE_STEPS,
       warm        from the network's prediction (lbm_set_fields),
-      warm+smooth from the prediction, with the smoothing step.
+      warm+smooth from the prediction, with the smoothing step,
+      consistent, consistent+smooth  (on request) from the prediction made
+                  consistent by consistent_start, without and with the
+                  smoothing step.
     An equilibrium start from any field that is not the scheme's own steady
     state excites the undamped staggered-momentum mode of the D2Q9 streaming;
     the smoothing step (mean of two consecutive states) removes it.  Each
@@ -524,15 +552,19 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
             b.set_mask(c, m)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if mode.startswith("warm"):
-            for c, (rho, ux, uy) in enumerate(predict_fields(net, scales, masks, params)):
-                b.set_fields(c, rho, ux, uy)
-        t_inf = time.perf_counter() - t0
         extra = 0
+        if mode.startswith(("warm", "consistent")):
+            pred = predict_fields(net, scales, masks, params)
+            for c, (rho, ux, uy) in enumerate(pred):
+                b.set_fields(c, rho, ux, uy)
+            if mode.startswith("consistent"):
+                consistent_start(b, pred, masks)
+                extra += CONSISTENT_STEPS
+        t_inf = time.perf_counter() - t0
         if mode.endswith("smooth"):
             b.step(SETTLE_STEPS)
             b.smooth_step()
-            extra = SETTLE_STEPS + 1
+            extra += SETTLE_STEPS + 1
         steps = b.run_to_steady(tol, check_every, max_steps)
         steps = np.where(steps > 0, steps + extra, steps)
         wall = time.perf_counter() - t0
@@ -545,17 +577,24 @@ def warm_vs_cold(net, scales, params, nx=256, ny=128, U=0.05, tol=1e-8, check_ev
         out[mode] = dict(reached=int((r["steps"] > 0).sum()), seconds=round(r["seconds"], 3))
         if mode.startswith("warm"):
             out["inference_seconds"] = round(r["inference_seconds"], 3)
+        if mode.startswith("consistent"):
+            out[mode]["start_seconds"] = round(r["inference_seconds"], 3)
     # against the plain scheme from rest
     if "cold" in res:
         for mode in res:
             if mode != "cold":
                 out[mode]["vs_cold"] = _compare(res, "cold", mode)
-    # the network's own gain: the same start-up treatment with and without it
-    for warm, cold in (("warm+smooth", "cold+smooth"), ("warm", "cold")):
+    # the network's own gain: the same start-up treatment with and without
+    # it; the consistent start against the equilibrium start of the same
+    # prediction
+    for key, warm, cold in (("network_gain", "warm+smooth", "cold+smooth"),
+                            ("network_gain", "warm", "cold"),
+                            ("consistent_gain", "consistent+smooth", "warm+smooth"),
+                            ("consistent_gain", "consistent", "warm")):
         if warm in res and cold in res:
             c = _compare(res, cold, warm)
             c["wall_speedup"] = float(res[cold]["seconds"] / res[warm]["seconds"])
-            out[f"network_gain_{warm}_vs_{cold}"] = c
+            out[f"{key}_{warm}_vs_{cold}"] = c
     out["per_case"] = [dict(Re=round(p["Re"], 1), r=p["r"],
                             **{m: int(res[m]["steps"][c]) for m in res}) for c, p in enumerate(params)]
     return out
@@ -721,9 +760,15 @@ if __name__ == "__main__":
     ap.add_argument("--out", default=None)
     ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
                     help="skip training: evaluate saved weights on --test-cases unseen cases")
+    ap.add_argument("--modes", default=",".join(MODES),
+                    help="starts to evaluate, comma-separated, of " + ", ".join(MODES + EXTRA_MODES))
     a = ap.parse_args()
     if a.eval_only:
-        cmp = evaluate(a.eval_only, a.test_cases)
+        modes = tuple(m for m in a.modes.split(",") if m)
+        unknown = [m for m in modes if m not in MODES + EXTRA_MODES]
+        if unknown:
+            ap.error(f"unknown modes {unknown}")
+        cmp = evaluate(a.eval_only, a.test_cases, modes=modes, log=lambda m: print(m, flush=True))
         if a.out:
             import os
             os.makedirs(a.out, exist_ok=True)
