@@ -158,7 +158,7 @@ int lbm_steps_per_launch(const lbm_ctx *ctx);
  *                      (1.12 collisions per lattice update against 1.30);
  *                      LBM_FP32_DEV only;
  *   LBM_FORM_AUTO      (the default) staged for LBM_FP32_DEV once it has at
- *                      least 1024 tiles, else register.
+ *                      least 512 tiles, else register.
  * Errors: LBM_E_INVAL (ctx NULL, an unknown form, LBM_FORM_STAGED with a
  * precision other than LBM_FP32_DEV). */
 enum { LBM_FORM_AUTO = 0, LBM_FORM_REGISTER = 1, LBM_FORM_STAGED = 2 };

@@ -551,13 +551,13 @@ constexpr int tile2_rows() { return 8; }
 constexpr int kStagedRows = 24, kStagedThreads = 768, kStagedWaves = 6;
 
 // The automatic choice takes the staged form from this many of its
-// workgroups up (four per CU).  Its fixed cost per launch is higher (7-8 us
-// per step on lattices of up to 256 x 512 nodes, against 4.5-5 us), so
+// workgroups up (two per CU).  Its fixed cost per launch is higher (7-8 us
+// per step on lattices of up to 256 x 512 nodes, against 5-5.5 us), so
 // smaller lattices run the register form: measured per step with cavity
-// boundaries, register / staged, 512 x 1024 9.2 / 9.7 us, 1024 x 1024 (688
-// staged workgroups) 13.0 / 13.0, 1024 x 2048 (1376) 20.9 / 19.6, 2048 x 4096
-// 89.4 / 77.1.
-constexpr int kStagedMinGroups = 1024;
+// boundaries, register / staged, 512 x 1024 (344 staged workgroups) 9.64 /
+// 9.72 us, 1024 x 1024 (688) 13.46 / 12.95, 1024 x 2048 21.84 / 19.51,
+// 2048 x 4096 88.30 / 76.67.
+constexpr int kStagedMinGroups = 512;
 
 int staged_groups(const Geometry &G) {
     return ((G.nx + kWave - 1) / kWave) * ((G.ny + kStagedRows - 1) / kStagedRows);

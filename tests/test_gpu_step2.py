@@ -147,14 +147,14 @@ def test_step_counts_and_the_state_one_step_back():
 
 
 def test_two_step_form_choice_and_validation():
-    """The automatic form: staged for FP32 storage from 1024 of its 64 x 24
+    """The automatic form: staged for FP32 storage from 512 of its 64 x 24
     tiles up, register below and in every other precision; the staged form
     cannot be asked of another precision."""
     for (nx, ny, prec), want in (((150, 70, L.LBM_FP32_DEV), REG),
-                                 ((1024, 1024, L.LBM_FP32_DEV), REG),     # 688 tiles
-                                 ((2048, 768, L.LBM_FP32_DEV), STAGED),   # 1024 tiles
-                                 ((2048, 768, L.LBM_FP64), REG),
-                                 ((2048, 768, L.LBM_FP32_DEV_F64), REG)):
+                                 ((512, 1024, L.LBM_FP32_DEV), REG),      # 344 tiles
+                                 ((1024, 768, L.LBM_FP32_DEV), STAGED),   # 512 tiles
+                                 ((1024, 1024, L.LBM_FP64), REG),
+                                 ((1024, 1024, L.LBM_FP32_DEV_F64), REG)):
         p, lat = make("periodic", nx, ny, 0, prec)
         assert lat.two_step_form() == want, (nx, ny, prec)
         if prec != L.LBM_FP32_DEV:
