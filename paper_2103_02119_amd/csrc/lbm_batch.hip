@@ -677,8 +677,9 @@ static void commit_steps(lbm_batch *b, long n) {
     }
 }
 
-// Host bookkeeping after `launches` two-step launches (2 launches steps) of
-// every active case: the other buffer then holds the state two steps back.
+// Host bookkeeping after `launches` two-step launches (2 x launches steps)
+// of every active case: the other buffer then holds the state two steps
+// back, which no residual can use.
 static void commit_pairs(lbm_batch *b, long launches) {
     if (launches <= 0) return;
     for (int c = 0; c < b->n; ++c) {
