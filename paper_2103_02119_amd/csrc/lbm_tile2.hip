@@ -212,10 +212,12 @@ __device__ __forceinline__ void tile2_body(const S *__restrict__ src, S *__restr
             r1[qy][qx] = R(0);
         }
     }
-    const R rc0 = sum9(f0);
-    const R rc1 = has1 ? sum9(f1) : R(0);
-    r1[py0 + 1][px0 + 1] = (LOAD == 0 || n0.in) ? rc0 : R(0);
-    if (has1) r1[py1 + 1][px1 + 1] = (LOAD == 0 || n1.in) ? rc1 : R(0);
+    // (a node beyond a wall has no values; its density slot holds 0 and is
+    // never read by a gradient, which takes the node's own density there)
+    const R rc0 = (LOAD == 0 || n0.in) ? sum9(f0) : R(0);
+    const R rc1 = has1 && (LOAD == 0 || n1.in) ? sum9(f1) : R(0);
+    r1[py0 + 1][px0 + 1] = rc0;
+    if (has1) r1[py1 + 1][px1 + 1] = rc1;
     __syncthreads();
 
     // ---- B: collide P, step-t post-collision values to LDS
@@ -246,8 +248,11 @@ __device__ __forceinline__ void tile2_body(const S *__restrict__ src, S *__restr
     const NodeAt no = at(ox, oj);
     const bool active = ox < G.nx && oj < G.ny;
     R g[9];
-    if (LOAD == 0 || no.in) pull_lds<S, R, C::PW, C::PH, WALLS>(pb, tx + 2, ty + 2, no.x, no.j, G, K, g);
-    const R rco = sum9(g);
+    R rco = R(0);
+    if (LOAD == 0 || no.in) {
+        pull_lds<S, R, C::PW, C::PH, WALLS>(pb, tx + 2, ty + 2, no.x, no.j, G, K, g);
+        rco = sum9(g);
+    }
     // ring of the tile: rows j0 - 1 and j0 + TY (66 each), columns x0 - 1 and
     // x0 + 64 (TY each), in the C frame (origin x0 - 1, j0 - 1)
     int cx = 0, cy = 0;
