@@ -61,3 +61,34 @@ def test_trained_network_gains_over_the_same_start_without_it(record_property):
     assert cmp["warm+smooth"]["reached"] >= cmp["cold+smooth"]["reached"] - 2
     assert own["compared"] >= 40
     assert own["step_speedup_total"] > 1.05, own
+
+
+def test_consistent_start_keeps_the_predicted_velocity():
+    """consistent_start (the Mei et al. style start the evaluation can
+    compare) leaves every fluid node at the predicted velocity, to rounding,
+    while the density develops away from the predicted one."""
+    import numpy as np
+
+    from paper_2103_02119_amd import inputs as I
+
+    print("case: consistent start 64x32", flush=True)
+    nx, ny, U = 64, 32, 0.05
+    params = [dict(Re=400.0, r=0.5, mask_seed=5), dict(Re=900.0, r=1.0, mask_seed=9)]
+    masks = [I.cavity_obstacles(nx, ny, p["mask_seed"]) for p in params]
+    b = WS.L.Batch(WS.cavity_cases(params, nx, ny, U), precision=WS.L.LBM_FP64)
+    pred = []
+    for c, m in enumerate(masks):
+        b.set_mask(c, m)
+        rho, ux, uy = I.random_fields(40 + c, nx, ny)
+        fluid = m == 0
+        pred.append((np.where(fluid, rho, 1.0), np.where(fluid, 0.5 * ux, 0.0),
+                     np.where(fluid, 0.5 * uy, 0.0)))
+        b.set_fields(c, *pred[c])
+    WS.consistent_start(b, pred, masks, steps=20)
+    for c, m in enumerate(masks):
+        rho, ux, uy = b.moments(c)
+        fl = m == 0
+        assert np.abs(ux - pred[c][1])[fl].max() < 1e-14
+        assert np.abs(uy - pred[c][2])[fl].max() < 1e-14
+        assert np.abs(rho - pred[c][0])[fl].max() > 1e-6
+    b.close()
