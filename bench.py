@@ -516,7 +516,8 @@ def bench_sweep(args):
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "algorithmic_bytes_per_launch": bytes_per_lu * nodes * spl,
-            "kernel": ("lbm::batch_tile2_kernel" if spl == 2 else
+            "kernel": (("lbm::batch_staged_kernel" if b.two_step_form() == L.LBM_FORM_STAGED
+                        else "lbm::batch_tile2_kernel") if spl == 2 else
                        "lbm::batch_tile_kernel" if tile else "lbm::batch_step_kernel"),
             "steps_per_launch": spl,
             "bytes_per_lu": bytes_per_lu,

@@ -57,6 +57,11 @@ typedef struct {
                             kernel (lbm_set_steps_per_launch) on 64 x 8 block tiles,
                             the single steps with the tile kernel; 1: one step per
                             launch.  Results are bit-identical either way. */
+    int two_step_form;   /* form of the two-step kernel (lbm_set_two_step_form):
+                            LBM_FORM_AUTO (default: staged for LBM_FP32_DEV, else
+                            register), LBM_FORM_REGISTER (64 x 8 block tiles) or
+                            LBM_FORM_STAGED (64 x 24 block tiles, LBM_FP32_DEV only);
+                            lbm_batch_autotune may change an automatic choice */
 } lbm_batch_opts;
 
 typedef struct lbm_batch lbm_batch;
@@ -138,8 +143,10 @@ long lbm_batch_steps_done(const lbm_batch *b, int c);
  * the one-node-per-thread tile kernel on 64 x 8 block tiles with three grid
  * sizes; it then reports 8 rows), trial_steps >= 1 launches each, and keeps
  * the fastest.  With two steps per launch in force it times only the
- * two-step kernel's persistent grid (one block tile per workgroup, or 8, 4
- * or 2 workgroups per CU) and reports 8 rows.  Setting a mask later returns the batch to the marching
+ * two-step kernel: its persistent grid (one block tile per workgroup, or a
+ * few workgroups per CU) in each form allowed (the register form; the staged
+ * form too for LBM_FP32_DEV unless two_step_form fixes one), and reports the
+ * chosen form's block-tile rows (8 or 24).  Setting a mask later returns the batch to the marching
  * kernel.  The trial launches recompute one step from the current state
  * without committing it, so no case advances; the residual of every case
  * needs a step afterwards.  rows_out / workgroups_out (may be NULL) receive
@@ -150,6 +157,10 @@ int lbm_batch_autotune(lbm_batch *b, int trial_steps, int *rows_out, int *workgr
  * or taken with two steps per launch, when no case has a mask), 0 for the
  * marching kernel; -1 for a NULL batch. */
 int lbm_batch_uses_tile_kernel(const lbm_batch *b);
+
+/* Form of the batch's two-step kernel (LBM_FORM_REGISTER or LBM_FORM_STAGED);
+ * LBM_E_INVAL for a NULL batch. */
+int lbm_batch_two_step_form(const lbm_batch *b);
 
 /* Steps per launch of the next long run: 2 while two steps per launch are
  * allowed (lbm_batch_opts.steps_per_launch) and no case has a mask, else 1;

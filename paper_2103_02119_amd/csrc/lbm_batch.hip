@@ -76,7 +76,12 @@ struct lbm_batch {
     bool graph_ok;
     // two steps per launch (lbm_batch_opts.steps_per_launch != 1, no mask)
     int spl_opt;                // 0 automatic, 1, 2
+    int form2;                  // kFormRegister (64 x 8 block tiles) or kFormStaged (64 x 24)
     int workgroups2;            // persistent grid of the two-step kernel
+    BatchTile *d_tiles24;       // 64 x kBatchStagedRows block tiles of the active cases
+    int *d_ntiles24;
+    int tile24_cap;
+    int ntiles24;
     hipGraphExec_t graph2;      // captured runs of two-step launches
     bool graph2_ok;
     char err[512];
@@ -142,6 +147,11 @@ static int block_tiles(const Geometry &G) {
     return G.nseg * ((G.ny + kBatchTileRows - 1) / kBatchTileRows);
 }
 
+// block tiles of the batched staged two-step kernel for one case
+static int staged_tiles(const Geometry &G) {
+    return G.nseg * ((G.ny + kBatchStagedRows - 1) / kBatchStagedRows);
+}
+
 // Tile list of the active cases, uploaded with its count: block tiles in tile
 // mode, wavefront tiles of the march otherwise.  A mask on any case ends tile
 // mode (its generic loads would be slower than the march's near-solid tiles).
@@ -175,6 +185,25 @@ static int upload_tiles(lbm_batch *b) {
                                  hipMemcpyHostToDevice, b->stream));
     HIP_OK(b, hipMemcpyAsync(b->d_ntiles, &b->ntiles, sizeof(int), hipMemcpyHostToDevice,
                              b->stream));
+    // the staged two-step form's own list of taller block tiles
+    std::vector<BatchTile> t24;
+    if (b->tile_mode && b->d_tiles24) {
+        t24.reserve(b->tile24_cap);
+        for (int c = 0; c < b->n; ++c) {
+            if (!b->active[c]) continue;
+            const Geometry &G = b->G[c];
+            const int nty = (G.ny + kBatchStagedRows - 1) / kBatchStagedRows;
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < G.nseg; ++tx) t24.push_back(BatchTile{c, tx, ty, 0});
+        }
+        b->ntiles24 = static_cast<int>(t24.size());
+        if (b->ntiles24 > b->tile24_cap) return fail(b, LBM_E_DEVICE, "tile list overflow");
+        if (b->ntiles24)
+            HIP_OK(b, hipMemcpyAsync(b->d_tiles24, t24.data(), t24.size() * sizeof(BatchTile),
+                                     hipMemcpyHostToDevice, b->stream));
+        HIP_OK(b, hipMemcpyAsync(b->d_ntiles24, &b->ntiles24, sizeof(int),
+                                 hipMemcpyHostToDevice, b->stream));
+    }
     // the host vector and count must outlive the copies
     HIP_OK(b, hipStreamSynchronize(b->stream));
     return LBM_OK;
@@ -227,10 +256,18 @@ static hipError_t launch(lbm_batch *b, int flip, int force_pull, int wgs) {
                              force_pull, wgs, b->stream);
 }
 
-static hipError_t launch2(lbm_batch *b, int flip, int wgs) {
+static hipError_t launch2_form(lbm_batch *b, int form, int flip, int wgs) {
+    if (form == kFormStaged)
+        return launch_batch_staged(b->prec, b->coll, b->higher_unit, b->buf[0], b->buf[1],
+                                   b->d_tiles24, b->d_ntiles24, b->d_cases, b->d_geoms, b->d_Kf,
+                                   flip, wgs, b->stream);
     return launch_batch_tile2(b->prec, b->coll, b->higher_unit, b->buf[0], b->buf[1], b->d_tiles,
                               b->d_ntiles, b->d_cases, b->d_geoms, b->d_Kd, b->d_Kf, flip, wgs,
                               b->stream);
+}
+
+static hipError_t launch2(lbm_batch *b, int flip, int wgs) {
+    return launch2_form(b, b->form2, flip, wgs);
 }
 
 static int ensure_graph2(lbm_batch *b) {
@@ -309,7 +346,7 @@ extern "C" int lbm_batch_destroy(lbm_batch *b) {
     if (b->graph2) (void)hipGraphExecDestroy(b->graph2);
     void *ptrs[] = {b->buf[0], b->buf[1], b->d_cases, b->d_geoms, b->d_Kd, b->d_Kf, b->d_H,
                     b->d_tiles, b->d_ntiles, b->d_items, b->d_case_first, b->d_case_count,
-                    b->d_partials, b->d_out, b->d_stage};
+                    b->d_partials, b->d_out, b->d_stage, b->d_tiles24, b->d_ntiles24};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (unsigned char *p : b->d_mask)
@@ -338,6 +375,10 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
         return fail(nullptr, LBM_E_INVAL, "graph_steps must be even and >= 2");
     if (o.steps_per_launch < 0 || o.steps_per_launch > 2)
         return fail(nullptr, LBM_E_INVAL, "steps_per_launch must be 0, 1 or 2");
+    if (o.two_step_form < 0 || o.two_step_form > 2)
+        return fail(nullptr, LBM_E_INVAL, "two_step_form must be 0, 1 or 2");
+    if (o.two_step_form == kFormStaged && o.precision != LBM_FP32_DEV)
+        return fail(nullptr, LBM_E_INVAL, "the staged two-step form needs LBM_FP32_DEV");
     lbm_batch *b = new (std::nothrow) lbm_batch();
     if (!b) return fail(nullptr, LBM_E_NOMEM, "out of host memory");
     b->n = ncases;
@@ -346,6 +387,9 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
     b->coll = o.collision;
     b->graph_steps = o.graph_steps;
     b->spl_opt = o.steps_per_launch;
+    // automatic: the staged form for FP32 storage and arithmetic
+    b->form2 = o.two_step_form != kFormAuto ? o.two_step_form
+                                            : (o.precision == LBM_FP32_DEV ? kFormStaged : kFormRegister);
     b->vbytes = f32_storage(o.precision) ? sizeof(float) : sizeof(double);
     snprintf(b->err, sizeof(b->err), "no error");
     try {
@@ -445,6 +489,13 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
     ALLOC(b->d_Kf, ncases * sizeof(Consts<float>));
     ALLOC(b->d_H, ncases * sizeof(HostSide));
     ALLOC(b->d_ntiles, sizeof(int));
+    if (o.precision == LBM_FP32_DEV) {
+        int cap24 = 0;
+        for (int c = 0; c < ncases; ++c) cap24 += staged_tiles(b->G[c]);
+        b->tile24_cap = cap24;
+        ALLOC(b->d_tiles24, static_cast<size_t>(cap24 > 0 ? cap24 : 1) * sizeof(BatchTile));
+        ALLOC(b->d_ntiles24, sizeof(int));
+    }
     ALLOC(b->d_case_first, ncases * sizeof(int));
     ALLOC(b->d_case_count, ncases * sizeof(int));
     ALLOC(b->d_out, ncases * 4 * sizeof(double));
@@ -471,7 +522,8 @@ extern "C" int lbm_batch_create(int ncases, const lbm_case *cases, const lbm_bat
         b->workgroups = o.workgroups > 0 ? o.workgroups : auto_workgroups(b->ntiles);
         // two-step grid: one block tile per workgroup (persistent beyond that)
         int nbt = 0;
-        for (int c = 0; c < ncases; ++c) nbt += block_tiles(b->G[c]);
+        for (int c = 0; c < ncases; ++c)
+            nbt += b->form2 == kFormStaged ? staged_tiles(b->G[c]) : block_tiles(b->G[c]);
         b->workgroups2 = o.workgroups > 0 ? o.workgroups : (nbt > 0 ? nbt : 1);
         for (int c = 0; c < ncases; ++c) {
             HIP_OK(b, launch_init_feq(b->prec, case_ptr(b, c, 0), nullptr, nullptr, nullptr,
@@ -852,44 +904,57 @@ extern "C" long lbm_batch_steps_done(const lbm_batch *b, int c) {
 }
 
 // With two steps per launch the autotuner times the two-step kernel's
-// persistent grid: one block tile per workgroup, or 8, 4 or 2 workgroups per
-// CU.  Each trial recomputes the same pair of steps into the other buffer.
+// persistent grid in each form the precision allows (the register form on
+// 64 x 8 block tiles; for LBM_FP32_DEV also the staged form on 64 x 24): one
+// block tile per workgroup, or a few workgroups per CU.  Each trial
+// recomputes the same pair of steps into the other buffer.
 static int autotune_two_step(lbm_batch *b, int trial_steps, int *rows_out, int *workgroups_out) {
     int rc = ensure_tiles(b);
     if (rc != LBM_OK) return rc;
-    const int nbt = b->ntiles;
     hipEvent_t e0, e1;
     HIP_OK(b, hipEventCreate(&e0));
     HIP_OK(b, hipEventCreate(&e1));
     float best = 1e30f;
-    int best_wgs = b->workgroups2;
-    for (int wgs : {nbt, 256 * 8, 256 * 4, 256 * 2}) {
-        if (nbt == 0) break;
-        if (wgs > nbt) wgs = nbt;
-        hipError_t e = launch2(b, 0, wgs);
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int i = 0; i < trial_steps && e == hipSuccess; ++i) e = launch2(b, 0, wgs);
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            rc = fail(b, LBM_E_DEVICE, "autotune launch failed: %s", hipGetErrorString(e));
-            break;
+    int best_wgs = b->workgroups2, best_form = b->form2;
+    const bool staged_ok = b->prec == kFP32Dev && b->opts.two_step_form != kFormRegister;
+    const bool register_ok = b->opts.two_step_form != kFormStaged;
+    for (int form : {kFormRegister, kFormStaged}) {
+        if ((form == kFormStaged && !staged_ok) || (form == kFormRegister && !register_ok)) continue;
+        const int nt = form == kFormStaged ? b->ntiles24 : b->ntiles;
+        // resident workgroups per CU: 2 (staged, 77 KB of LDS), 3 or more (register)
+        const int per_cu[] = {form == kFormStaged ? 4 : 8, form == kFormStaged ? 2 : 4,
+                              form == kFormStaged ? 1 : 2};
+        for (int wgs : {nt, 256 * per_cu[0], 256 * per_cu[1], 256 * per_cu[2]}) {
+            if (nt == 0) break;
+            if (wgs > nt) wgs = nt;
+            hipError_t e = launch2_form(b, form, 0, wgs);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int i = 0; i < trial_steps && e == hipSuccess; ++i) e = launch2_form(b, form, 0, wgs);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(b, LBM_E_DEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_wgs = wgs;
+                best_form = form;
+            }
         }
-        if (ms < best) {
-            best = ms;
-            best_wgs = wgs;
-        }
+        if (rc != LBM_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LBM_OK) return rc;
+    b->form2 = best_form;
     b->workgroups2 = best_wgs;
     b->graph2_ok = false;
     // the other buffer of every case was overwritten by the trials
     for (int c = 0; c < b->n; ++c) b->form_prev[c] = kEmpty;
-    if (rows_out) *rows_out = kBatchTileRows;
+    if (rows_out) *rows_out = best_form == kFormStaged ? kBatchStagedRows : kBatchTileRows;
     if (workgroups_out) *workgroups_out = best_wgs;
     return LBM_OK;
 }
@@ -990,7 +1055,10 @@ extern "C" int lbm_batch_launch_shape(const lbm_batch *b, int *rows_per_wave, in
     // (tile mode reports its block-tile rows and block tiles; with two steps
     // per launch, the two-step kernel's grid)
     const bool tile = tile_mode_wanted(b);
-    if (rows_per_wave) *rows_per_wave = tile ? kBatchTileRows : b->rows;
+    if (rows_per_wave)
+        *rows_per_wave = two_step_on(b) && b->form2 == kFormStaged ? kBatchStagedRows
+                         : tile                                     ? kBatchTileRows
+                                                                    : b->rows;
     if (workgroups) *workgroups = two_step_on(b) ? b->workgroups2 : b->workgroups;
     if (tiles) {
         // count without touching the device when the list is stale
@@ -1010,6 +1078,11 @@ extern "C" int lbm_batch_uses_tile_kernel(const lbm_batch *b) {
 extern "C" int lbm_batch_steps_per_launch(const lbm_batch *b) {
     if (!b) return LBM_E_INVAL;
     return two_step_on(b) ? 2 : 1;
+}
+
+extern "C" int lbm_batch_two_step_form(const lbm_batch *b) {
+    if (!b) return LBM_E_INVAL;
+    return b->form2;
 }
 
 extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {

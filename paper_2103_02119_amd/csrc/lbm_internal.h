@@ -100,6 +100,7 @@ struct BatchRed {
 };
 constexpr int kBatchRedNodes = 4096;  // nodes per reduction work item
 constexpr int kBatchTileRows = 8;     // rows of a block tile of the batched tile kernel
+constexpr int kBatchStagedRows = 24;  // rows of a block tile of the batched staged two-step kernel
 
 // ---- host helpers shared by the single-lattice and batch front ends ----
 // (implemented in lbm_api.hip; the lbm.h types are opaque here)
@@ -202,6 +203,12 @@ hipError_t launch_batch_tile2(int prec, int coll, bool higher_unit, void *buf0, 
                               const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
                               const Geometry *geoms, const Consts<double> *Kd,
                               const Consts<float> *Kf, int flip, int workgroups, hipStream_t st);
+// the staged two-step form over a list of 64 x kBatchStagedRows block tiles
+// (LBM_FP32_DEV only)
+hipError_t launch_batch_staged(int prec, int coll, bool higher_unit, void *buf0, void *buf1,
+                               const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                               const Geometry *geoms, const Consts<float> *Kf, int flip,
+                               int workgroups, hipStream_t st);
 // per-case residual sums of the batch: out[4 c + 0..3] as for launch_residual,
 // over the cases named by the reduction items (items of a case are contiguous)
 hipError_t launch_batch_residual(int prec, const void *buf0, const void *buf1,

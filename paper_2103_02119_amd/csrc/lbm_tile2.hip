@@ -437,6 +437,30 @@ __device__ __forceinline__ void tile2_body_staged(const S *__restrict__ src, S *
 #undef load
 }
 
+// The staged form on one 64 x TY tile at (x0, j0), by the tile's class.
+template <typename S, typename R, bool DEV, int COLL, bool HU, int TY, int NT>
+__device__ __forceinline__ void tile2_staged_tile(const S *__restrict__ src, S *__restrict__ dst,
+                                                  const Geometry &G, const Consts<R> &K, int x0,
+                                                  int j0, R (*pb)[T2S<TY, NT>::PH][T2S<TY, NT>::PW],
+                                                  R *rr) {
+    using C = T2S<TY, NT>;
+    R(*r1)[C::QW] = reinterpret_cast<R(*)[C::QW]>(rr);
+    R(*r2)[C::CW] = reinterpret_cast<R(*)[C::CW]>(rr);
+    const bool walls = G.bc[kXmin] != kPeriodic || G.bc[kYmin] != kPeriodic;
+    const bool rows_in = G.buf_ok && j0 >= 4 && j0 + TY + 4 <= G.ny;
+    const bool cols_in = x0 >= 4 && x0 + kWave + 4 <= G.nx;
+    if (rows_in && cols_in)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 0, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else if (rows_in && !walls)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 1, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else if (rows_in)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 1, true>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else if (walls)
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, true>(src, dst, G, K, x0, j0, pb, r1, r2);
+    else
+        tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+}
+
 template <typename S, typename R, bool DEV, int COLL, bool HU, int TY, int NT, int WPE>
 __global__ void __launch_bounds__(NT, WPE)
 tile2_staged_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geometry G,
@@ -448,6 +472,9 @@ tile2_staged_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geomet
     const int nb = static_cast<int>(gridDim.x);
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
     if (b >= ntx * nty) return;                             // padding workgroup (whole block)
+    // (the tile's class is chosen here rather than through tile2_staged_tile:
+    // with the kernel arguments in scalar registers that form spills fewer
+    // of them)
     const int x0 = (b % ntx) * kWave, j0 = (b / ntx) * TY;
     R(*r1)[C::QW] = reinterpret_cast<R(*)[C::QW]>(rr);
     R(*r2)[C::CW] = reinterpret_cast<R(*)[C::CW]>(rr);
@@ -464,6 +491,34 @@ tile2_staged_kernel(const S *__restrict__ src, S *__restrict__ dst, const Geomet
         tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, true>(src, dst, G, K, x0, j0, pb, r1, r2);
     else
         tile2_body_staged<S, R, DEV, COLL, HU, TY, NT, 2, false>(src, dst, G, K, x0, j0, pb, r1, r2);
+}
+
+// Batched staged form: a persistent grid walks a list of 64 x TY block tiles
+// of all active cases (BatchTile {case, tile column, tile row}), every case
+// in pull form; case c reads buf[cur ^ flip] and writes the other buffer.
+template <typename S, typename R, bool DEV, int COLL, bool HU, int TY, int NT, int WPE>
+__global__ void __launch_bounds__(NT, WPE)
+batch_staged_kernel(S *__restrict__ buf0, S *__restrict__ buf1,
+                    const BatchTile *__restrict__ tiles, const int *__restrict__ ntiles,
+                    const BatchCase *__restrict__ cases, const Geometry *__restrict__ geoms,
+                    const Consts<R> *__restrict__ Ks, int flip) {
+    using C = T2S<TY, NT>;
+    __shared__ R pb[9][C::PH][C::PW];
+    __shared__ R rr[C::QH * C::QW];
+    const int n = *ntiles;
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const BatchTile td = tiles[t];
+        const int c = __builtin_amdgcn_readfirstlane(td.c);
+        const int tcol = __builtin_amdgcn_readfirstlane(td.seg);
+        const int trow = __builtin_amdgcn_readfirstlane(td.chunk);
+        const int cur = __builtin_amdgcn_readfirstlane(cases[c].cur) ^ flip;
+        const long long off = cases[c].off;
+        const S *src = (cur ? buf1 : buf0) + off;
+        S *dst = (cur ? buf0 : buf1) + off;
+        tile2_staged_tile<S, R, DEV, COLL, HU, TY, NT>(src, dst, geoms[c], Ks[c], tcol * kWave,
+                                                       trow * TY, pb, rr);
+        __syncthreads();  // the next tile reuses the LDS tiles
+    }
 }
 
 // The register form on one 64 x TY tile at (x0, j0): interior tiles take
@@ -649,6 +704,27 @@ static hipError_t batch_tile2_dispatch(int coll, bool hu, void *b0, void *b1,
         if (hu) LBM_BT2(kRNR, true); else LBM_BT2(kRNR, false);
     }
 #undef LBM_BT2
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_staged(int prec, int coll, bool hu, void *b0, void *b1,
+                               const BatchTile *tiles, const int *ntiles, const BatchCase *cases,
+                               const Geometry *geoms, const Consts<float> *Kf, int flip, int wgs,
+                               hipStream_t st) {
+    if (prec != kFP32Dev) return hipErrorInvalidValue;  // the staged form is FP32 only
+    static_assert(kBatchStagedRows == kStagedRows, "block tiles of the staged form");
+    constexpr int TY = kStagedRows, NT = kStagedThreads, WPE = kStagedWaves;
+    const dim3 grid(wgs), block(NT);
+    float *s0 = static_cast<float *>(b0), *s1 = static_cast<float *>(b1);
+#define LBM_BST(CO, H)                                                                             \
+    hipLaunchKernelGGL((batch_staged_kernel<float, float, true, CO, H, TY, NT, WPE>), grid, block, \
+                       0, st, s0, s1, tiles, ntiles, cases, geoms, Kf, flip)
+    if (coll == kRC) {
+        if (hu) LBM_BST(kRC, true); else LBM_BST(kRC, false);
+    } else {
+        if (hu) LBM_BST(kRNR, true); else LBM_BST(kRNR, false);
+    }
+#undef LBM_BST
     return hipGetLastError();
 }
 

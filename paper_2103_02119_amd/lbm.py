@@ -40,6 +40,7 @@ BATCH_EXPORTS = ("lbm_batch_default_opts", "lbm_batch_create", "lbm_batch_set_fi
                  "lbm_batch_run_to_steady", "lbm_batch_moments", "lbm_batch_get_populations",
                  "lbm_batch_set_populations", "lbm_batch_steps_done", "lbm_batch_autotune",
                  "lbm_batch_uses_tile_kernel", "lbm_batch_steps_per_launch",
+                 "lbm_batch_two_step_form",
                  "lbm_batch_launch_shape", "lbm_batch_last_error", "lbm_batch_destroy")
 
 
@@ -93,6 +94,7 @@ class lbm_batch_opts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("tile_kernel", ctypes.c_int),
         ("steps_per_launch", ctypes.c_int),
+        ("two_step_form", ctypes.c_int),
     ]
 
 
@@ -201,6 +203,8 @@ def load():
     L.lbm_batch_uses_tile_kernel.restype = ctypes.c_int
     L.lbm_batch_steps_per_launch.argtypes = [_B]
     L.lbm_batch_steps_per_launch.restype = ctypes.c_int
+    L.lbm_batch_two_step_form.argtypes = [_B]
+    L.lbm_batch_two_step_form.restype = ctypes.c_int
     L.lbm_batch_last_error.argtypes = [_B]
     L.lbm_batch_last_error.restype = ctypes.c_char_p
     L.lbm_batch_destroy.argtypes = [_B]
@@ -632,6 +636,13 @@ def lbm_batch_steps_per_launch(b) -> int:
     return k
 
 
+def lbm_batch_two_step_form(b) -> int:
+    f = load().lbm_batch_two_step_form(b)
+    if f < 0:
+        raise LbmError(f, "NULL batch")
+    return f
+
+
 def lbm_batch_autotune(b, trial_steps=5):
     r, w = ctypes.c_int(), ctypes.c_int()
     _bcheck(load().lbm_batch_autotune(b, int(trial_steps), ctypes.byref(r), ctypes.byref(w)), b)
@@ -658,11 +669,12 @@ class Batch:
 
     def __init__(self, cases, collision=LBM_RC, precision=LBM_FP64, corrections=True,
                  rows_per_wave=0, workgroups=0, graph_steps=0, stream=None, tile_kernel=False,
-                 steps_per_launch=0):
+                 steps_per_launch=0, two_step_form=LBM_FORM_AUTO):
         """stream: a hipStream_t handle (e.g. torch.cuda.Stream().cuda_stream)
         or None for a stream the batch creates; tile_kernel: step with the
         tile kernel from the start (else the autotuner chooses);
-        steps_per_launch: 0 automatic (two while no case has a mask), 1, 2."""
+        steps_per_launch: 0 automatic (two while no case has a mask), 1, 2;
+        two_step_form: LBM_FORM_AUTO, LBM_FORM_REGISTER or LBM_FORM_STAGED."""
         self.shapes = [(c.nx, c.ny) for c in cases]
         self.n = len(cases)
         o = lbm_batch_default_opts()
@@ -672,6 +684,7 @@ class Batch:
         o.stream = stream
         o.tile_kernel = 1 if tile_kernel else 0
         o.steps_per_launch = int(steps_per_launch)
+        o.two_step_form = int(two_step_form)
         self.b = lbm_batch_create(cases, o)
 
     def set_fields(self, c, rho=None, ux=None, uy=None):
@@ -718,6 +731,9 @@ class Batch:
 
     def steps_per_launch(self):
         return lbm_batch_steps_per_launch(self.b)
+
+    def two_step_form(self):
+        return lbm_batch_two_step_form(self.b)
 
     def launch_shape(self):
         return lbm_batch_launch_shape(self.b)

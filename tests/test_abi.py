@@ -223,6 +223,7 @@ def test_null_handles_are_rejected_before_touching_the_device():
     assert lib.lbm_batch_step(None, 1) == L.LBM_E_INVAL
     assert lib.lbm_batch_destroy(None) == L.LBM_OK
     assert lib.lbm_batch_steps_per_launch(None) == L.LBM_E_INVAL
+    assert lib.lbm_batch_two_step_form(None) == L.LBM_E_INVAL
 
 
 def test_stream_copy_validates_before_touching_the_device():

@@ -316,20 +316,24 @@ def test_tile_kernel_returns_when_the_masks_are_removed():
     b.close()
 
 
-@pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP32_DEV])
+@pytest.mark.parametrize("prec,form", [(L.LBM_FP64, L.LBM_FORM_AUTO),
+                                       (L.LBM_FP32_DEV, L.LBM_FORM_REGISTER),
+                                       (L.LBM_FP32_DEV, L.LBM_FORM_STAGED)])
 @pytest.mark.parametrize("coll", [L.LBM_RC, L.LBM_RNR])
 @pytest.mark.parametrize("general", [False, True])
-def test_two_steps_per_launch_batch_is_bitwise_the_one_step_batch(prec, coll, general):
+def test_two_steps_per_launch_batch_is_bitwise_the_one_step_batch(prec, form, coll, general):
     """Pairs of steps per launch (graph replays of pairs, single pair
     launches and the closing single steps), through a deactivated case and a
     case reset mid-run, against the same batch at one step per launch:
     populations, step counts and residuals bit for bit.  A mask turns the
     pairs off."""
-    announce("batch two-step", prec, coll, general)
+    announce("batch two-step", prec, form, coll, general)
     rates = GENERAL if general else None
     bs = [L.Batch(cases_of(SPECS, rates), collision=coll, precision=prec, graph_steps=4,
-                  steps_per_launch=k) for k in (1, 0)]
+                  steps_per_launch=k, two_step_form=form) for k in (1, 0)]
     assert bs[0].steps_per_launch() == 1 and bs[1].steps_per_launch() == 2
+    want = form if form != L.LBM_FORM_AUTO else L.LBM_FORM_REGISTER  # FP64: register
+    assert bs[1].two_step_form() == want
     for b in bs:
         for c, spec in enumerate(SPECS):
             b.set_fields(c, *I.random_fields(300 + c, spec[0], spec[1]))
@@ -369,6 +373,33 @@ def test_two_step_batch_autotune_and_run_to_steady():
     steps = [b.run_to_steady(1e-6, 50, 3000) for b in bs]
     assert np.array_equal(steps[0], steps[1])
     for c in range(3):
+        assert np.array_equal(bs[0].get_populations(c), bs[1].get_populations(c)), c
+    assert np.array_equal(bs[0].residuals(), bs[1].residuals())
+    for b in bs:
+        b.close()
+
+
+def test_two_step_batch_form_choice_and_autotune_in_fp32():
+    """FP32 storage: the staged form by default, the register form on
+    request, the staged form refused for FP64; the autotuner's choice of form
+    and grid keeps the results bit for bit those of one step per launch."""
+    announce("batch two-step form choice")
+    b = L.Batch(cases_of(SPECS[:3]), precision=L.LBM_FP32_DEV)
+    assert b.two_step_form() == L.LBM_FORM_STAGED
+    b.close()
+    with pytest.raises(L.LbmError):
+        L.Batch(cases_of(SPECS[:3]), precision=L.LBM_FP64, two_step_form=L.LBM_FORM_STAGED)
+    bs = [L.Batch(cases_of(SPECS), precision=L.LBM_FP32_DEV, graph_steps=8, steps_per_launch=k)
+          for k in (1, 0)]
+    for b in bs:
+        b.step(3)
+    rows, wgs = bs[1].autotune(2)
+    form = bs[1].two_step_form()
+    assert (rows, form) in ((8, L.LBM_FORM_REGISTER), (24, L.LBM_FORM_STAGED))
+    assert bs[1].launch_shape()[:2] == (rows, wgs)
+    for b in bs:
+        b.step(40)
+    for c in range(len(SPECS)):
         assert np.array_equal(bs[0].get_populations(c), bs[1].get_populations(c)), c
     assert np.array_equal(bs[0].residuals(), bs[1].residuals())
     for b in bs:
