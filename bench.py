@@ -16,8 +16,10 @@ the warm-up steps) are resident in HBM when timing starts.
 Beside the headline it reports: the library's own streaming copy of one
 population buffer (the copy ceiling), the one-step-per-launch kernel, the
 same workload in FP64 and with the raw-moment (RNR) collision, the
-cache-resident 512 x 1024 cavity, time to steady state, and the FP64 CPU
-oracle timed on a bounded sample on the host.
+cache-resident 512 x 1024 cavity, time to steady state (cold and from the
+learned warm start), the FP32-storage velocity error against FP64 at the
+cavity's converged state and over 50 000 steps of the shear layer, and the
+FP64 CPU oracle timed on a bounded sample on the host.
 
 Prints ONE JSON line.  The roofline is that of the dominant kernel: its
 algorithmic bytes per launch (9 reads + 9 writes per node) over its mean
@@ -423,6 +425,30 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def shear_fp32_50k(nu=4e-2, steps=50_000, every=5000):
+    """FP32 deviation storage against FP64 on the 2048 x 8192 shear layer
+    over its configured 50 000 steps, RC, at nu = 4e-2 (tau 1.5): the
+    velocity difference (max |du| / max |u|) at every `every` steps.  The
+    headline's nu = 6e-3 does not survive 50 000 steps in RC (FP64 blows up
+    near 36 000), and at nu <= 2e-2 the roll-up of the layers amplifies
+    perturbations of rounding size for a while (stability.py --study fp32)."""
+    from paper_2103_02119_amd import lbm as L
+    from paper_2103_02119_amd import stability as S
+
+    r = S.shear_layer(nu=nu, steps=steps, check_every=every, compare_every=every,
+                      collisions=(L.LBM_RC,))
+    x = r["RC"]
+    diffs = x["fp32_vs_fp64"]
+    return dict(workload="shear 2048x8192 r=0.25 kappa=80 delta=0.05 u0=0.04 doubly periodic",
+                nu=nu, tau=r["tau"], cs2=r["cs2"], steps=steps, collision="RC",
+                blowup_step_fp64=x["blowup_step_fp64"], blowup_step_fp32=x["blowup_step_fp32"],
+                compared_every=every, max_error=x["max_fp32_vs_fp64"],
+                final_error=diffs[-1][1] if diffs else None, bar=1e-5,
+                meets_bar=(x["max_fp32_vs_fp64"] is not None and len(diffs) == steps // every
+                           and x["max_fp32_vs_fp64"] < 1e-5),
+                reference="the FP64 run of the same length", seconds=x["seconds"])
+
+
 def warm_start_section(n_cases=64, max_steps=400_000):
     """The learned warm start on unseen 256 x 128 cavities with obstacles
     (seeded Re in [100, 5000], a in {0.25, 0.5, 1}): steps and wall time to
@@ -764,6 +790,9 @@ def main():
         if not args.no_steady:
             out["time_to_steady"], out["fp32_steady_error"] = cavity_steady()
             progress("cavity to steady state done")
+            out["fp32_shear_50k"] = shear_fp32_50k()
+            progress(f"shear layer fp32 vs fp64 over 50000 steps done: "
+                     f"max {out['fp32_shear_50k']['max_error']:.2e}")
             out["time_to_steady"]["warm_start"] = warm_start_section()
             progress("warm-start section done")
         if not args.no_cpu_baseline:

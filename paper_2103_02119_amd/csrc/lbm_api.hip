@@ -462,9 +462,9 @@ extern "C" int lbm_set_fields(lbm_ctx *c, const double *rho, const double *ux, c
 }
 
 // Steps per launch a run takes: two (the temporally blocked kernel) where
-// the tile kernel applies (no obstacle mask) and the caller asked for it or,
-// automatically, once the two population buffers exceed the 256 MB Infinity
-// Cache, so that a step is bound by HBM traffic; one otherwise.
+// the tile kernel applies (no obstacle mask) unless the caller asked for one
+// (the automatic choice takes two on every such lattice: measured faster
+// from 64 x 32 nodes up, in the Infinity Cache and beyond it); one otherwise.
 static int steps_per_launch(const lbm_ctx *c) {
     if (!uses_tile_kernel(c->G) || c->steps_per_launch == 1) return 1;
     return 2;

@@ -10,7 +10,9 @@ round advances in the same launches.
                     U = 0.2, cs2 = 0.1 (the paper's Table 6 study);
   shear_layer       the doubly periodic shear layer: the step at which each
                     collision model blows up, and the FP32-deviation run's
-                    velocity difference from the FP64 run until then.
+                    velocity difference from the FP64 run until then;
+  perturbation_growth  the FP64 shear layer's response to a population
+                    perturbation of FP32 rounding's size made at a given step.
 
 A case is unstable when a residual check (every `check_every` steps and at
 the end) meets a non-finite velocity.
@@ -107,11 +109,12 @@ def max_reynolds(grids=TABLE6_GRIDS, a=0.5, U=0.2, cs2=0.1, collisions=(L.LBM_RC
 
 
 def shear_layer(nx=2048, ny=8192, a=0.25, nu=1e-4, u0=0.04, kappa=80.0, delta=0.05, cs2=0.04,
-                steps=50_000, check_every=500, compare_every=5000, log=None):
-    """RC and RNR, FP64 and FP32 deviations, on the doubly periodic shear
-    layer: blow-up step (None if it survives `steps`) and the FP32-vs-FP64
-    velocity difference (max-norm relative to max |u| of the FP64 run) at
-    every `compare_every` steps while both are finite."""
+                steps=50_000, check_every=500, compare_every=5000,
+                collisions=(L.LBM_RC, L.LBM_RNR), log=None):
+    """FP64 and FP32 deviations, per collision model, on the doubly periodic
+    shear layer: blow-up step (None if it survives `steps`) and the
+    FP32-vs-FP64 velocity difference (max-norm relative to max |u| of the
+    FP64 run) at every `compare_every` steps while both are finite."""
     import torch
 
     from . import inputs as I
@@ -120,7 +123,7 @@ def shear_layer(nx=2048, ny=8192, a=0.25, nu=1e-4, u0=0.04, kappa=80.0, delta=0.
     tau = nu / cs2 + 0.5
     rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
     out = {}
-    for coll in (L.LBM_RC, L.LBM_RNR):
+    for coll in collisions:
         name = "RC" if coll == L.LBM_RC else "RNR"
         lats = {p: L.Lattice(nx, ny, a, rates, cs2=cs2, collision=coll, precision=p)
                 for p in (L.LBM_FP64, L.LBM_FP32_DEV)}
@@ -154,11 +157,50 @@ def shear_layer(nx=2048, ny=8192, a=0.25, nu=1e-4, u0=0.04, kappa=80.0, delta=0.
         for lat in lats.values():
             lat.close()
         out[name] = dict(blowup_step_fp64=blow[L.LBM_FP64], blowup_step_fp32=blow[L.LBM_FP32_DEV],
-                         fp32_vs_fp64=diffs, seconds=round(time.perf_counter() - t0, 1))
+                         fp32_vs_fp64=diffs,
+                         max_fp32_vs_fp64=max((d for _, d in diffs), default=None),
+                         seconds=round(time.perf_counter() - t0, 1))
         if log:
             log(f"shear_layer {name}: {out[name]}")
     return dict(nx=nx, ny=ny, a=a, nu=nu, tau=tau, cs2=cs2, steps=steps, check_every=check_every,
                 **out)
+
+
+def perturbation_growth(nx=2048, ny=8192, a=0.25, nu=1.2e-2, u0=0.04, kappa=80.0, delta=0.05,
+                        cs2=0.04, kick_at=36_000, until=40_000, every=1000, amp=1e-7,
+                        collision=L.LBM_RC, log=None):
+    """How the FP64 scheme itself treats a perturbation of FP32 rounding's
+    size: two FP64 runs of the shear layer, one of them with every
+    population multiplied by 1 + amp xi (xi ~ U(-1, 1), seeded) at step
+    `kick_at`; their velocity difference (max-norm relative to max |u|)
+    every `every` steps up to `until`."""
+    from . import inputs as I
+
+    rho0, ux0, uy0 = I.shear_layer(nx, ny, a, u0=u0, kappa=kappa, delta=delta)
+    tau = nu / cs2 + 0.5
+    rates = [1.0, 1.0, 1.0, 1.0, 1.0 / tau, 1.0 / tau, 1.0, 1.0, 1.0]
+    ref, kicked = (L.Lattice(nx, ny, a, rates, cs2=cs2, collision=collision, precision=L.LBM_FP64)
+                   for _ in range(2))
+    for lat in (ref, kicked):
+        lat.set_fields(rho0, ux0, uy0)
+        lat.step(kick_at)
+    f = kicked.get_populations()
+    f *= I.relative_noise(6, nx, ny, amp=amp)
+    kicked.set_populations(f)
+    del f
+    diffs = []
+    for done in range(kick_at + every, until + 1, every):
+        for lat in (ref, kicked):
+            lat.step(every)
+        _, a0, b0 = ref.moments()
+        _, a1, b1 = kicked.moments()
+        diffs.append((done, float(np.hypot(a1 - a0, b1 - b0).max() / np.hypot(a0, b0).max())))
+        if log:
+            log(f"perturbation growth nu={nu:g}: step {done}: {diffs[-1][1]:.3e}")
+    ref.close()
+    kicked.close()
+    return dict(nx=nx, ny=ny, a=a, nu=nu, tau=tau, cs2=cs2, amp=amp, kick_at=kick_at,
+                collision="RC" if collision == L.LBM_RC else "RNR", difference=diffs)
 
 
 def shear_layer_sweep(nus=(1e-4, 2e-4, 4e-4, 8e-4, 1.6e-3), steps=20_000, check_every=100,
@@ -227,7 +269,8 @@ if __name__ == "__main__":
     import json
 
     ap = argparse.ArgumentParser(description="stability margins of RC-LBM and RNR-LBM")
-    ap.add_argument("--study", choices=["lid", "reynolds", "shear", "margin", "all"], default="all")
+    ap.add_argument("--study", choices=["lid", "reynolds", "shear", "margin", "fp32", "all"],
+                    default="all")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     log = lambda s: print(s, flush=True)  # noqa: E731
@@ -249,6 +292,14 @@ if __name__ == "__main__":
         res["shear_layer_margin_50k"] = [
             shear_layer_margin(nu_lo=1e-3, nu_hi=2e-2, rounds=5, steps=50_000, precision=p, log=log)
             for p in (L.LBM_FP64, L.LBM_FP32_DEV)]
+    if args.study == "fp32":
+        # FP32 storage against FP64 over the configured 50 000 steps at stable viscosities,
+        # and what the FP64 scheme makes of a 1e-7 perturbation during the roll-up
+        res["shear_layer_fp32_50k"] = [
+            shear_layer(nu=nu, steps=50_000, check_every=2500, compare_every=2500, log=log)
+            for nu in (1.2e-2, 2e-2, 4e-2)]
+        res["perturbation_growth"] = [perturbation_growth(nu=nu, log=log)
+                                      for nu in (1.2e-2, 4e-2)]
     text = json.dumps(res)
     print(text, flush=True)
     if args.out:
