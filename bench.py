@@ -282,7 +282,9 @@ def roofline_of(r, copy_gbs, traffic=None):
         "traffic": traffic[0] if traffic else None,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "traffic_over_algorithmic": traffic[1] if traffic else None,
-        "valu_issue": valu_ceiling_of(r, traffic[2] if traffic else None),
+        "valu_issue": valu_ceiling_of(r, traffic[2] if traffic else None,
+                                      traffic[3] if traffic else None,
+                                      "fp32" if r.get("value_bytes", 4) == 4 else "fp64"),
         "kernel": r["kernel"],
         "steps_per_launch": k,
         "algorithmic_bytes_per_launch": bpl,
@@ -320,26 +322,42 @@ def traffic_of(key):
         tr = json.load(fh)
     if tr.get("kernel_sha") == kernel_sha() and key in tr.get("per_launch", {}):
         e = tr["per_launch"][key]
-        return e["bytes_per_launch"], e["ratio"], e.get("valu_insts_per_64_lu")
+        return e["bytes_per_launch"], e["ratio"], e.get("valu_insts_per_64_lu"), e.get("flops_per_lu")
     return None
 
 
 # one wave64 vector instruction per CU per cycle (four SIMDs of 16 lanes)
 N_CU, CLOCK_GHZ = 256, 2.4
+# MI355X vector peaks (TFLOP/s): FP32 as published (counts packed FP32
+# instructions, which this library does not use), FP32 without them (one FMA
+# per lane per cycle: 256 CUs x 64 lanes x 2 x 2.4 GHz), FP64
+PEAK_TFLOPS = {"fp32": 157.3, "fp32_unpacked": 78.6, "fp64": 78.6}
 
 
-def valu_ceiling_of(r, valu_per_64):
+def valu_ceiling_of(r, valu_per_64, flops_per_lu=None, arith="fp32"):
     """The kernel's vector-ALU issue ceiling in lattice updates per second:
     256 CUs x 2.4 GHz x one wave64 instruction per CU per cycle, over the
-    VALU instructions per lattice update that the counters measured."""
+    VALU instructions per lattice update that the counters measured; and the
+    floating-point rate those counters give, against the vector peaks."""
     if not valu_per_64:
         return None
     peak = N_CU * CLOCK_GHZ * 1e9 / (valu_per_64 / 64) / 1e9  # GLUPS
     got = r["steps_per_launch"] * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
-    return {"bound": "alu", "unit": "GLUPS", "achieved": round(got, 1), "peak": round(peak, 1),
-            "frac": round(got / peak, 4), "valu_insts_per_64_lu": valu_per_64,
-            "peak_from": "256 CUs x 2.4 GHz x one wave64 VALU instruction per CU per cycle "
-                         "(unpacked), over SQ_INSTS_VALU per lattice update (profiles/)"}
+    out = {"bound": "alu", "unit": "GLUPS", "achieved": round(got, 1), "peak": round(peak, 1),
+           "frac": round(got / peak, 4), "valu_insts_per_64_lu": valu_per_64,
+           "peak_from": "256 CUs x 2.4 GHz x one wave64 VALU instruction per CU per cycle "
+                        "(unpacked), over SQ_INSTS_VALU per lattice update (profiles/)"}
+    if flops_per_lu:
+        tf = got * flops_per_lu / 1e3
+        out["flops"] = {"flops_per_lu": flops_per_lu, "achieved_tflops": round(tf, 2),
+                        "arithmetic": arith, "peak_tflops": PEAK_TFLOPS[arith],
+                        "frac": round(tf / PEAK_TFLOPS[arith], 4)}
+        if arith == "fp32":
+            out["flops"]["peak_tflops_unpacked"] = PEAK_TFLOPS["fp32_unpacked"]
+            out["flops"]["frac_unpacked"] = round(tf / PEAK_TFLOPS["fp32_unpacked"], 4)
+        out["flops"]["from"] = "executed FP adds, multiplies, FMAs (x2) and transcendentals " \
+                               "counted by rocprofv3 (profiles/traffic.json)"
+    return out
 
 
 def cpu_baseline(name, collision, budget_s=10.0):
