@@ -505,6 +505,44 @@ def test_full_size_shear_layer_2048x8192_sampled(prec, tol):
     lat.close()
 
 
+@pytest.mark.parametrize("prec,nx,ny,tol", [(L.LBM_FP64, 8192, 8192, TOL64),
+                                            (L.LBM_FP32_DEV, 16384, 8192, 1e-6)])
+def test_population_buffers_beyond_4gib(prec, nx, ny, tol):
+    """Maximum sizes: a population buffer beyond 4 GiB (4.8 GB here) is out
+    of reach of 32-bit buffer offsets, so every tile of the one- and
+    two-step kernels takes the generic loader and store with 64-bit
+    addresses.  On the doubly periodic a = 0.25 shear layer, sampled nodes
+    of one step match the oracle, and three steps taken as a two-step
+    launch and a one-step launch equal three one-step launches bit for
+    bit."""
+    a, cs2 = 0.25, 0.04
+    rates = O.paper_rates(6e-3 / cs2 + 0.5)
+    assert L.lbm_required_bytes(nx, ny, prec) > 4 * 2 ** 30
+    p = O.make_params(nx, ny, a, cs2, rates)
+    fields = I.shear_layer(nx, ny, a)
+    announce("buffers beyond 4 GiB, one step per launch", prec, nx, ny)
+    lat = L.Lattice(nx, ny, a, rates, cs2=cs2, precision=prec)
+    lat.set_steps_per_launch(1)
+    lat.set_fields(*fields)
+    lat.step(2)
+    f_before = lat.get_populations()
+    lat.step(1)
+    worst = _sampled_check(p, lat, f_before, tol, nsamp=24)
+    print("sampled nodes against the oracle:", worst, flush=True)
+    del f_before
+    one = lat.get_populations()
+    lat.close()
+    announce("buffers beyond 4 GiB, two steps per launch", prec, nx, ny)
+    lat = L.Lattice(nx, ny, a, rates, cs2=cs2, precision=prec)
+    lat.set_fields(*fields)
+    assert lat.steps_per_launch() == 2
+    lat.step(3)
+    assert lat.steps_done == 3
+    two = lat.get_populations()
+    lat.close()
+    assert np.array_equal(one, two)
+
+
 # ---------------------------------------------------------------- state operations
 
 @pytest.mark.parametrize("prec", [L.LBM_FP64, L.LBM_FP64_DEV])
