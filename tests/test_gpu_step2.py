@@ -195,3 +195,36 @@ def test_full_size_shear_layer_two_steps_bit_identical(prec, form, want):
         lat.close()
     for u, v in zip(*out):
         assert np.array_equal(u, v)
+
+
+def test_zero_steps_change_nothing():
+    """The empty run: lbm_step(ctx, 0) and lbm_batch_step(b, 0) enqueue
+    nothing, so the populations, the step count and the residual of the last
+    step stay as they were, right after creation and mid-run."""
+    from paper_2103_02119_amd import warmstart as WS
+
+    announce("zero steps")
+    p, lat = make("cavity", 70, 25, L.LBM_RC, L.LBM_FP32_DEV)
+    lat.set_populations(random_state(p, seed=7))
+    f0 = lat.get_populations()
+    lat.step(0)
+    assert lat.steps_done == 0 and np.array_equal(lat.get_populations(), f0)
+    lat.step(3)
+    f3, R3 = lat.get_populations(), lat.residual()
+    lat.step(0)
+    assert lat.steps_done == 3 and np.array_equal(lat.get_populations(), f3)
+    assert lat.residual() == R3
+    lat.close()
+    b = L.Batch(WS.cavity_cases([dict(Re=400.0, r=0.5), dict(Re=900.0, r=1.0)], 64, 32, 0.05),
+                precision=L.LBM_FP32_DEV)
+    g0 = [b.get_populations(c) for c in range(2)]
+    b.step(0)
+    assert all(b.steps_done(c) == 0 and np.array_equal(b.get_populations(c), g0[c])
+               for c in range(2))
+    b.step(5)
+    g5, R5 = [b.get_populations(c) for c in range(2)], b.residuals()
+    b.step(0)
+    assert all(b.steps_done(c) == 5 and np.array_equal(b.get_populations(c), g5[c])
+               for c in range(2))
+    assert np.array_equal(b.residuals(), R5)
+    b.close()
