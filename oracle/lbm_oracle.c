@@ -36,6 +36,14 @@
  *     Eq. 34-35 (m - m^{eq,r}), with no forcing term;
  *   - bounce-back: f_i(x_f, t+1) = ft_ibar(x_f, t) - (feq_ibar - feq_i)(rho_w, u_w)
  *     with rho_w = rho0; a link that crosses a moving wall uses that wall.
+ *
+ * Parity unpinned: the conventions the paper leaves open have no value in
+ * the paper or the mathematics that fixes them, so the GPU path agrees with
+ * this file on them but nothing independent checks them -- the wall
+ * neighbour's density in the gradient, rho_w = rho0, the corner rule for a
+ * link that crosses two faces, and the initial state f = feq(rho, u) with no
+ * non-equilibrium part.  (The lid and the corner rule together are checked
+ * only indirectly, by the primary-vortex centres the paper prints.)
  */
 #include "lbm_oracle.h"
 
