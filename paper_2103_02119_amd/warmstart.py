@@ -741,6 +741,61 @@ def evaluate(weights=WEIGHTS, n_test=64, test_seed=77, max_steps=400_000, modes=
     return warm_vs_cold(net, scales, test, max_steps=max_steps, modes=modes, log=log)
 
 
+def conv_flops(net):
+    """Multiply-adds x 2 of the network's 3x3 convolutions for one forward
+    pass of its batch (the pooling, upsampling, head and loss are left out)."""
+    total = 0
+    for cv in net.layers():
+        h, w = net._res(int(cv.name[1]))
+        total += 2 * net.N * h * w * 9 * (cv.c1 + cv.c2) * cv.cout
+    return total
+
+
+def nn_throughput(batch=16, reps=20, H=128, W=256, seed=5):
+    """Rate of the network's kernels on seeded random inputs: forward passes,
+    and whole training steps (forward, masked MSE, backward, Adam), timed
+    between device synchronizations.  A training step runs the 3x3
+    convolutions three times (forward, data gradient except for the first
+    layer, weight gradient)."""
+    import torch
+
+    net = WarmStartNet(H, W, batch, seed=seed)
+    g = np.random.Generator(np.random.PCG64(seed))
+    M0 = batch * H * W
+    x0 = torch.from_numpy(g.uniform(-1, 1, M0 * CIN).astype(np.float32)).cuda()
+    tgt = torch.from_numpy(g.normal(0, 1, M0 * COUT).astype(np.float32)).cuda()
+    fluid = torch.ones(M0, dtype=torch.uint8, device="cuda")
+    cw = torch.tensor((0.25, 1.0, 1.0), dtype=torch.float32, device="cuda")
+
+    def train_step():
+        net.forward(x0)
+        net.loss_grad(tgt, fluid, M0, cw)
+        net.backward(net.gpred)
+        net.adam(1e-4)
+
+    net.forward(x0)
+    train_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(x0)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        train_step()
+    torch.cuda.synchronize()
+    step = (time.perf_counter() - t0) / reps
+    f = conv_flops(net)
+    first = net.enc[0][0]
+    f_first = 2 * batch * H * W * 9 * (first.c1 + first.c2) * first.cout
+    f_step = 3 * f - f_first
+    return dict(batch=batch, H=H, W=W, conv_gflop_forward=round(f / 1e9, 2),
+                forward_ms=round(1e3 * fwd, 3), forward_tflops=round(f / fwd / 1e12, 1),
+                train_step_ms=round(1e3 * step, 3), train_step_tflops=round(f_step / step / 1e12, 1),
+                samples_per_s=round(batch / step, 1), peak_bf16_tflops=2500.0)
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -760,10 +815,14 @@ if __name__ == "__main__":
     ap.add_argument("--out", default=None)
     ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
                     help="skip training: evaluate saved weights on --test-cases unseen cases")
+    ap.add_argument("--nn-throughput", action="store_true",
+                    help="time the network's forward pass and training step (batch 16) and exit")
     ap.add_argument("--modes", default=",".join(MODES),
                     help="starts to evaluate, comma-separated, of " + ", ".join(MODES + EXTRA_MODES))
     a = ap.parse_args()
-    if a.eval_only:
+    if a.nn_throughput:
+        print(json.dumps(nn_throughput()), flush=True)
+    elif a.eval_only:
         modes = tuple(m for m in a.modes.split(",") if m)
         unknown = [m for m in modes if m not in MODES + EXTRA_MODES]
         if unknown:
