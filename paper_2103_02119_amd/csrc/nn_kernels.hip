@@ -231,26 +231,65 @@ conv_wgrad_kernel(const bf16 *__restrict__ x1, int c1, const bf16 *__restrict__ 
             }
 }
 
-// gw[i] = sum_s part[s][i] in a fixed order
-__global__ void sum_splits_kernel(const float *__restrict__ part, int splits, size_t n,
-                                  float *__restrict__ gw) {
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+// gw[i] = sum_s part[s][i] in a fixed order: a block takes kSumOuts
+// consecutive outputs, its kSumGroups thread groups each sum every
+// kSumGroups-th split (s = group, group + kSumGroups, ...), and the group
+// sums are added in group order.
+constexpr int kSumOuts = 32, kSumGroups = 8;
+__global__ void __launch_bounds__(kSumOuts * kSumGroups)
+sum_splits_kernel(const float *__restrict__ part, int splits, size_t n, float *__restrict__ gw) {
+    __shared__ float red[kSumGroups][kSumOuts];
+    const int lo = static_cast<int>(threadIdx.x) % kSumOuts;
+    const int grp = static_cast<int>(threadIdx.x) / kSumOuts;
+    for (size_t base = static_cast<size_t>(blockIdx.x) * kSumOuts; base < n;
+         base += static_cast<size_t>(gridDim.x) * kSumOuts) {
+        const size_t i = base + lo;
         float s = 0.f;
-        for (int j = 0; j < splits; ++j) s += part[static_cast<size_t>(j) * n + i];
-        gw[i] = s;
+        if (i < n)
+            for (int j = grp; j < splits; j += kSumGroups) s += part[static_cast<size_t>(j) * n + i];
+        red[grp][lo] = s;
+        __syncthreads();
+        if (grp == 0 && i < n) {
+            float t = 0.f;
+            for (int q = 0; q < kSumGroups; ++q) t += red[q][lo];
+            gw[i] = t;
+        }
+        __syncthreads();  // red is reused by the next outputs
     }
 }
 
+int sum_grid(size_t n) {
+    size_t b = (n + kSumOuts - 1) / kSumOuts;
+    if (b > 65536) b = 65536;
+    return b < 1 ? 1 : static_cast<int>(b);
+}
+
 // per-block column sums of g[M][c] (block b covers rows b*rows .. ), then a
-// fixed-order sum over blocks
-__global__ void colsum_partial_kernel(const float *__restrict__ g, int M, int c, int rows,
-                                      float *__restrict__ part) {
+// fixed-order sum over blocks.  Within a block the threads form groups of W
+// columns (W = c, or the block width for wider rows); group q sums rows
+// r0 + q, r0 + q + G, ... and the G group sums are added in group order.
+constexpr int kColThreads = 256;
+__global__ void __launch_bounds__(kColThreads)
+colsum_partial_kernel(const float *__restrict__ g, int M, int c, int rows,
+                      float *__restrict__ part) {
+    __shared__ float red[kColThreads];
     const int r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
-    for (int j = threadIdx.x; j < c; j += blockDim.x) {
+    const int W = c < kColThreads ? c : kColThreads;
+    const int G = kColThreads / W;
+    const int t = static_cast<int>(threadIdx.x), grp = t / W, jl = t % W;
+    for (int j0 = 0; j0 < c; j0 += W) {
+        const int j = j0 + jl;
         float s = 0.f;
-        for (int r = r0; r < r1; ++r) s += g[static_cast<size_t>(r) * c + j];
-        part[static_cast<size_t>(blockIdx.x) * c + j] = s;
+        if (grp < G && j < c)
+            for (int r = r0 + grp; r < r1; r += G) s += g[static_cast<size_t>(r) * c + j];
+        red[t] = s;
+        __syncthreads();
+        if (grp == 0 && j < c) {
+            float tot = 0.f;
+            for (int q = 0; q < G; ++q) tot += red[q * W + jl];
+            part[static_cast<size_t>(blockIdx.x) * c + j] = tot;
+        }
+        __syncthreads();  // red is reused by the next columns
     }
 }
 
@@ -513,15 +552,15 @@ int lbm_nn_conv3x3_wgrad(const void *x1, int c1, const void *x2, int c2, int n, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return LBM_NN_E_DEVICE;
     const size_t nw = static_cast<size_t>(K) * cout;
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(nw)), dim3(256), 0, st, part,
-                       static_cast<int>(splits), nw, gw);
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(sum_grid(nw)), dim3(kSumOuts * kSumGroups), 0, st,
+                       part, static_cast<int>(splits), nw, gw);
     // bias gradient: column sums of gy, reusing the work space after the sum
     const int rows = 512;
     const int nb = static_cast<int>((M + rows - 1) / rows);
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3(nb), dim3(256), 0, st, gy,
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(nb), dim3(kColThreads), 0, st, gy,
                        static_cast<int>(M), cout, rows, part);
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(cout)), dim3(256), 0, st, part, nb,
-                       static_cast<size_t>(cout), gb);
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(sum_grid(cout)), dim3(kSumOuts * kSumGroups), 0,
+                       st, part, nb, static_cast<size_t>(cout), gb);
     return check(hipGetLastError());
 }
 
@@ -596,10 +635,12 @@ int lbm_nn_conv1x1_bwd(const void *x, const float *gy, int m, int cin, const flo
     hipLaunchKernelGGL(conv1x1_wgrad_partial_kernel, dim3(nb), dim3(256), 0, st,
                        static_cast<const bf16 *>(x), gy, m, cin, cout, rows, part);
     const size_t nw = static_cast<size_t>(cin) * cout;
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(nw)), dim3(256), 0, st, part, nb, nw, gw);
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3(nb), dim3(256), 0, st, gy, m, cout, rows, part);
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for(cout)), dim3(256), 0, st, part, nb,
-                       static_cast<size_t>(cout), gb);
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(sum_grid(nw)), dim3(kSumOuts * kSumGroups), 0, st,
+                       part, nb, nw, gw);
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(nb), dim3(kColThreads), 0, st, gy, m, cout,
+                       rows, part);
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(sum_grid(cout)), dim3(kSumOuts * kSumGroups), 0,
+                       st, part, nb, static_cast<size_t>(cout), gb);
     return check(hipGetLastError());
 }
 
@@ -624,7 +665,8 @@ int lbm_nn_mse(const float *pred, const float *target, const unsigned char *flui
     float *part = static_cast<float *>(work);
     hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(kThreads), 0, st, pred, target, fluid, m, c, cw,
                        1.f / count, grad, part);
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(1), dim3(256), 0, st, part, nb, static_cast<size_t>(1),
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(1), dim3(kSumOuts * kSumGroups), 0, st, part, nb,
+                       static_cast<size_t>(1),
                        loss);
     return check(hipGetLastError());
 }
