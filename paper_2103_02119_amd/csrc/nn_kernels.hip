@@ -301,71 +301,84 @@ __global__ void relu_bwd_kernel(const float *__restrict__ gy, const bf16 *__rest
         g[i] = static_cast<float>(y[i]) > 0.f ? gy[i] : 0.f;
 }
 
+// The pooling and upsampling kernels take the index type I: 32-bit unsigned
+// when every buffer they touch has fewer than 2^32 elements (the division
+// and modulo of the index then run in 32 bits), size_t otherwise.
+
 // 2 x 2 average pooling, x [N][H][W][c] -> y [N][H/2][W/2][c]
+template <typename I>
 __global__ void avgpool_fwd_kernel(const bf16 *__restrict__ x, int N, int H, int W, int c,
                                    bf16 *__restrict__ y) {
-    const int Ho = H / 2, Wo = W / 2;
-    const size_t n = static_cast<size_t>(N) * Ho * Wo * c;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const int ch = static_cast<int>(i % c);
-        const size_t p = i / c;
-        const int xo = static_cast<int>(p % Wo), yo = static_cast<int>((p / Wo) % Ho);
-        const size_t b = p / (static_cast<size_t>(Wo) * Ho);
-        const size_t base = ((b * H + 2 * yo) * W + 2 * xo) * c + ch;
-        const float s = static_cast<float>(x[base]) + static_cast<float>(x[base + c]) +
-                        static_cast<float>(x[base + static_cast<size_t>(W) * c]) +
-                        static_cast<float>(x[base + static_cast<size_t>(W) * c + c]);
+    const I Ho = H / 2, Wo = W / 2, C = c, Wi = W, Hi = H;
+    const I n = static_cast<I>(N) * Ho * Wo * C;
+    for (I i = blockIdx.x * static_cast<I>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<I>(gridDim.x) * blockDim.x) {
+        const I ch = i % C;
+        const I p = i / C;
+        const I xo = p % Wo, yo = (p / Wo) % Ho;
+        const I b = p / (Wo * Ho);
+        const I base = ((b * Hi + 2 * yo) * Wi + 2 * xo) * C + ch;
+        const float s = static_cast<float>(x[base]) + static_cast<float>(x[base + C]) +
+                        static_cast<float>(x[base + Wi * C]) +
+                        static_cast<float>(x[base + Wi * C + C]);
         y[i] = (bf16)(0.25f * s);
     }
 }
 
 // gx [N][H][W][c] (+)= gy [N][H/2][W/2][c] / 4 on each of the 2 x 2 sources
+template <typename I>
 __global__ void avgpool_bwd_kernel(const float *__restrict__ gy, int N, int H, int W, int c,
                                    float *__restrict__ gx, int accumulate) {
-    const size_t n = static_cast<size_t>(N) * H * W * c;
-    const int Ho = H / 2, Wo = W / 2;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const int ch = static_cast<int>(i % c);
-        const size_t p = i / c;
-        const int xx = static_cast<int>(p % W), yy = static_cast<int>((p / W) % H);
-        const size_t b = p / (static_cast<size_t>(W) * H);
-        const float v = 0.25f * gy[((b * Ho + yy / 2) * Wo + xx / 2) * c + ch];
+    const I Hi = H, Wi = W, C = c, Ho = H / 2, Wo = W / 2;
+    const I n = static_cast<I>(N) * Hi * Wi * C;
+    for (I i = blockIdx.x * static_cast<I>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<I>(gridDim.x) * blockDim.x) {
+        const I ch = i % C;
+        const I p = i / C;
+        const I xx = p % Wi, yy = (p / Wi) % Hi;
+        const I b = p / (Wi * Hi);
+        const float v = 0.25f * gy[((b * Ho + yy / 2) * Wo + xx / 2) * C + ch];
         gx[i] = accumulate ? gx[i] + v : v;
     }
 }
 
 // nearest upsampling by 2, x [N][H][W][c] -> y [N][2H][2W][c]
+template <typename I>
 __global__ void upsample_fwd_kernel(const bf16 *__restrict__ x, int N, int H, int W, int c,
                                     bf16 *__restrict__ y) {
-    const int Ho = 2 * H, Wo = 2 * W;
-    const size_t n = static_cast<size_t>(N) * Ho * Wo * c;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const int ch = static_cast<int>(i % c);
-        const size_t p = i / c;
-        const int xo = static_cast<int>(p % Wo), yo = static_cast<int>((p / Wo) % Ho);
-        const size_t b = p / (static_cast<size_t>(Wo) * Ho);
-        y[i] = x[((b * H + yo / 2) * W + xo / 2) * c + ch];
+    const I Hi = H, Wi = W, C = c, Ho = 2 * Hi, Wo = 2 * Wi;
+    const I n = static_cast<I>(N) * Ho * Wo * C;
+    for (I i = blockIdx.x * static_cast<I>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<I>(gridDim.x) * blockDim.x) {
+        const I ch = i % C;
+        const I p = i / C;
+        const I xo = p % Wo, yo = (p / Wo) % Ho;
+        const I b = p / (Wo * Ho);
+        y[i] = x[((b * Hi + yo / 2) * Wi + xo / 2) * C + ch];
     }
 }
 
 // gx [N][H][W][c] = sum of gy over the 2 x 2 copies
+template <typename I>
 __global__ void upsample_bwd_kernel(const float *__restrict__ gy, int N, int H, int W, int c,
                                     float *__restrict__ gx) {
-    const size_t n = static_cast<size_t>(N) * H * W * c;
-    const int Wo = 2 * W;
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-        const int ch = static_cast<int>(i % c);
-        const size_t p = i / c;
-        const int xx = static_cast<int>(p % W), yy = static_cast<int>((p / W) % H);
-        const size_t b = p / (static_cast<size_t>(W) * H);
-        const size_t q = ((b * 2 * H + 2 * yy) * Wo + 2 * xx) * c + ch;
-        gx[i] = (gy[q] + gy[q + c]) + (gy[q + static_cast<size_t>(Wo) * c] +
-                                       gy[q + static_cast<size_t>(Wo) * c + c]);
+    const I Hi = H, Wi = W, C = c, Wo = 2 * Wi;
+    const I n = static_cast<I>(N) * Hi * Wi * C;
+    for (I i = blockIdx.x * static_cast<I>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<I>(gridDim.x) * blockDim.x) {
+        const I ch = i % C;
+        const I p = i / C;
+        const I xx = p % Wi, yy = (p / Wi) % Hi;
+        const I b = p / (Wi * Hi);
+        const I q = ((b * 2 * Hi + 2 * yy) * Wo + 2 * xx) * C + ch;
+        gx[i] = (gy[q] + gy[q + C]) + (gy[q + Wo * C] + gy[q + Wo * C + C]);
     }
+}
+
+// true when buffers of `elems` elements can be indexed in 32 bits, with
+// room for one more grid stride (grid_for: at most 65536 x 256 threads)
+bool fits32(size_t elems) {
+    return elems + (static_cast<size_t>(1) << 24) < (static_cast<size_t>(1) << 32);
 }
 
 // 1x1 head: y[m][o] = sum_i x[m][i] w[i][o] + b[o] (FP32 out)
@@ -574,9 +587,15 @@ int lbm_nn_relu_bwd(const float *gy, const void *y, float *g, size_t count, void
 int lbm_nn_avgpool2_fwd(const void *x, int n, int h, int w, int c, void *y, void *stream) {
     if (!x || !y || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || c < 1) return LBM_NN_E_INVAL;
     const size_t cnt = static_cast<size_t>(n) * (h / 2) * (w / 2) * c;
-    hipLaunchKernelGGL(avgpool_fwd_kernel, dim3(grid_for(cnt)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x), n, h, w, c,
-                       static_cast<bf16 *>(y));
+    const auto *xp = static_cast<const bf16 *>(x);
+    auto *yp = static_cast<bf16 *>(y);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fits32(4 * cnt))
+        hipLaunchKernelGGL(avgpool_fwd_kernel<uint32_t>, dim3(grid_for(cnt)), dim3(256), 0, st, xp,
+                           n, h, w, c, yp);
+    else
+        hipLaunchKernelGGL(avgpool_fwd_kernel<size_t>, dim3(grid_for(cnt)), dim3(256), 0, st, xp,
+                           n, h, w, c, yp);
     return check(hipGetLastError());
 }
 
@@ -584,25 +603,41 @@ int lbm_nn_avgpool2_bwd(const float *gy, int n, int h, int w, int c, float *gx, 
                         void *stream) {
     if (!gy || !gx || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || c < 1) return LBM_NN_E_INVAL;
     const size_t cnt = static_cast<size_t>(n) * h * w * c;
-    hipLaunchKernelGGL(avgpool_bwd_kernel, dim3(grid_for(cnt)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), gy, n, h, w, c, gx, accumulate);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fits32(cnt))
+        hipLaunchKernelGGL(avgpool_bwd_kernel<uint32_t>, dim3(grid_for(cnt)), dim3(256), 0, st, gy,
+                           n, h, w, c, gx, accumulate);
+    else
+        hipLaunchKernelGGL(avgpool_bwd_kernel<size_t>, dim3(grid_for(cnt)), dim3(256), 0, st, gy,
+                           n, h, w, c, gx, accumulate);
     return check(hipGetLastError());
 }
 
 int lbm_nn_upsample2_fwd(const void *x, int n, int h, int w, int c, void *y, void *stream) {
     if (!x || !y || n < 1 || h < 1 || w < 1 || c < 1) return LBM_NN_E_INVAL;
     const size_t cnt = static_cast<size_t>(n) * 4 * h * w * c;
-    hipLaunchKernelGGL(upsample_fwd_kernel, dim3(grid_for(cnt)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x), n, h, w, c,
-                       static_cast<bf16 *>(y));
+    const auto *xp = static_cast<const bf16 *>(x);
+    auto *yp = static_cast<bf16 *>(y);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fits32(cnt))
+        hipLaunchKernelGGL(upsample_fwd_kernel<uint32_t>, dim3(grid_for(cnt)), dim3(256), 0, st, xp,
+                           n, h, w, c, yp);
+    else
+        hipLaunchKernelGGL(upsample_fwd_kernel<size_t>, dim3(grid_for(cnt)), dim3(256), 0, st, xp,
+                           n, h, w, c, yp);
     return check(hipGetLastError());
 }
 
 int lbm_nn_upsample2_bwd(const float *gy, int n, int h, int w, int c, float *gx, void *stream) {
     if (!gy || !gx || n < 1 || h < 1 || w < 1 || c < 1) return LBM_NN_E_INVAL;
     const size_t cnt = static_cast<size_t>(n) * h * w * c;
-    hipLaunchKernelGGL(upsample_bwd_kernel, dim3(grid_for(cnt)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), gy, n, h, w, c, gx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (fits32(4 * cnt))
+        hipLaunchKernelGGL(upsample_bwd_kernel<uint32_t>, dim3(grid_for(cnt)), dim3(256), 0, st, gy,
+                           n, h, w, c, gx);
+    else
+        hipLaunchKernelGGL(upsample_bwd_kernel<size_t>, dim3(grid_for(cnt)), dim3(256), 0, st, gy,
+                           n, h, w, c, gx);
     return check(hipGetLastError());
 }
 
