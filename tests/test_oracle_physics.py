@@ -8,6 +8,8 @@
 - Shear waves along x and along y decay with the same nu at every a.
 - Sound waves along x and y are damped at (nu + zeta) k^2 / 2 whatever
   uniform flow carries them (Galilean invariance of the normal stress).
+- A forced channel whose walls both move at U0 carries U0 plus the
+  Poiseuille parabola.
 - The local strain rate (Eq. 37-38) tracks the true velocity gradient.
 - Steady Couette flow between a fixed and a moving wall (Sec. 5.2, Eq. 57-59)
   is linear.
@@ -96,6 +98,34 @@ def test_taylor_green_decay_rate(orc, coll, a, cs2):
 @pytest.mark.parametrize("a,cs2", [(0.5, 0.16), (0.25, 0.04)])
 def test_taylor_green_fails_without_corrections(orc, a, cs2):
     assert abs(_decay_ratio(orc, "tgv", 32, a, cs2, 0.8, 0, corr=False) - 1) > 0.2
+
+
+def _moving_channel_error(orc, U0, coll, ny=16, a=0.5, cs2=0.16, nu=0.1, U=0.01, nx=4):
+    """Body-force channel whose two walls both move at (U0, 0) (Eq. 57-59 on
+    both y faces), started from the uniform flow U0: relative L2 error of
+    ux against U0 + the Poiseuille parabola after 8 H^2 / nu steps."""
+    H = ny * a
+    Fx = U * 2 * nu / (H / 2) ** 2
+    p = orc.make_params(nx, ny, a, cs2, orc.paper_rates(nu / cs2 + 0.5), force=(Fx, 0),
+                        bc=(0, 0, 2, 2), u_wall=((0, 0), (0, 0), (U0, 0), (U0, 0)),
+                        collision=coll)
+    f = orc.init(p, None, np.full((ny, nx), U0), np.zeros((ny, nx)))
+    _, ux, uy = orc.moments(p, orc.run(p, f, int(8 * H * H / nu)))
+    y = (np.arange(ny) + 0.5) * a
+    ua = U0 + U * (1 - (y - H / 2) ** 2 / (H / 2) ** 2)
+    return np.sqrt(((ux[:, 0] - ua) ** 2).sum() / ((ua - U0) ** 2).sum()), np.abs(uy).max()
+
+
+@pytest.mark.parametrize("coll", [0, 1])
+def test_poiseuille_in_a_moving_channel_is_the_shifted_profile(orc, coll):
+    """Galilean invariance of the forced channel: with both walls moving at
+    U0 = 0.05 or 0.1 along x, the steady profile is U0 plus the Poiseuille
+    parabola, to the accuracy of the channel at rest (0.80-0.82% at
+    a = 0.5, 16 nodes across)."""
+    e0, _ = _moving_channel_error(orc, 0.0, coll)
+    for U0 in (0.05, 0.1):
+        e, vmax = _moving_channel_error(orc, U0, coll)
+        assert e < 1e-2 and abs(e - e0) < 5e-4 and vmax < 1e-13, (U0, e, e0, vmax)
 
 
 def _sound_damping(orc, along, bg, coll=0, corr=True, a=0.5, cs2=0.1, tau=0.8, n=64,
